@@ -1,0 +1,188 @@
+/*
+ * cholinv.h -- C-ABI of libcholinv, the MI355X (gfx950) implementation of the
+ * reduced-operation inversion of Hermitian positive-definite matrices from
+ * Krishnamoorthy & Menon, "Matrix Inversion Using Cholesky Decomposition"
+ * (arXiv:1111.4144).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Matrices are dense and row major: element (i, j) of a matrix with leading
+ *   dimension ld sits at index i*ld + j (elements, not bytes).  The paper
+ *   prefers the upper factor R because its rows are contiguous (Section II).
+ * - Complex elements are interleaved (re, im) pairs of float (CI_C64) or
+ *   double (CI_C128).  Real types are CI_F32 and CI_F64.
+ * - Every matrix pointer is DEVICE memory owned by the caller; it must stay
+ *   valid until the work queued on `stream` has finished.  `stream` is a
+ *   hipStream_t passed as void* (NULL = the default stream).  Options structs
+ *   and n_host-style arguments are HOST memory, read before the call returns.
+ * - Inputs must be Hermitian (real: symmetric) positive definite.  Only the
+ *   upper triangle (i <= j) of an input A is read; its strict lower triangle
+ *   may hold anything, NaN included.  The imaginary part of a diagonal entry is
+ *   ignored.
+ * - Calls are asynchronous: they enqueue kernels on `stream` and return.  The
+ *   library never synchronises the stream and never allocates device memory on
+ *   the call path; scratch space is the caller's `work` buffer, sized by
+ *   chol_workspace_size().
+ *
+ * Errors
+ * ------
+ * The return value reports argument and launch errors at once:
+ *     0                    success (work queued)
+ *    -k  (1 <= k < 100)    argument number k (1-based) is invalid
+ *    CI_ERR_UNSUPPORTED    valid arguments but a combination this build lacks
+ *    CI_ERR_WORKSPACE      work_bytes smaller than chol_workspace_size()
+ *    CI_ERR_LAUNCH - e     a HIP launch failed with hipError_t e
+ * Numerical failure is never a return code.  `info` (device int32, one per
+ * matrix, may be NULL) receives 0, or the 1-based index i of the first pivot
+ * whose value is not a finite positive number: the radicand of eq. (3) for
+ * Cholesky, d_i of eq. (10) for LDL.  A NaN anywhere in the upper triangle
+ * reaches some pivot, so it is reported there.  The X of a failed matrix is
+ * filled with NaN.
+ */
+#ifndef CHOLINV_H
+#define CHOLINV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Element types. */
+enum { CI_F32 = 0, CI_F64 = 1, CI_C64 = 2, CI_C128 = 3 };
+
+/* Factorisation used by the inversion: Cholesky A = R^*R (Section II, eqs.
+ * 3-4; inversion Section IV.A) or LDL A = R^*DR (Section II.A, eqs. 10-11;
+ * inversion Section IV.B). */
+enum { CI_METHOD_CHOL = 0, CI_METHOD_LDL = 1 };
+
+/* Arithmetic.
+ * CI_PLAIN: everything in the element type (FP64 for CI_F64/CI_C128, FP32 for
+ *   CI_F32/CI_C64).
+ * CI_MIXED: element type must be CI_F32 or CI_C64.  The bulk of the work is
+ *   FP32; the pivot sums and square roots / reciprocals of eq. (3) or eq. (10)
+ *   are FP64; then ns_steps Newton-Schulz steps X <- X + X(I - AX) follow,
+ *   with the residual I - AX in FP64 (A and X upcast exactly) and the update
+ *   in FP32. */
+enum { CI_PLAIN = 0, CI_MIXED = 1 };
+
+typedef struct {
+    int32_t method;     /* CI_METHOD_CHOL or CI_METHOD_LDL                    */
+    int32_t precision;  /* CI_PLAIN or CI_MIXED                               */
+    int32_t ns_steps;   /* Newton-Schulz steps, 0..3 (CI_MIXED only)          */
+    int32_t fill_lower; /* 1: also write x_ji = conj(x_ij) (the Hermitian half
+                           "where needed", Section IV.A); 0: the strict lower
+                           triangle of X is left untouched                    */
+} ci_opts;
+
+#define CI_ERR_UNSUPPORTED (-2000)
+#define CI_ERR_WORKSPACE   (-2001)
+#define CI_ERR_LAUNCH      (-1000)
+
+/* Largest order handled by the batched small-matrix kernels (one matrix per
+ * lane or per lane group, held on chip).  Larger orders use the blocked
+ * single-matrix path of chol_inverse. */
+#define CI_SMALL_NMAX 64
+
+/*
+ * chol_factor -- Cholesky factorisation in place, Section II eqs. (3)-(4).
+ *   dtype     CI_F32 / CI_F64 / CI_C64 / CI_C128
+ *   batch     number of matrices (>= 0)
+ *   n         order, 0 <= n <= CI_SMALL_NMAX when batch > 1; any n >= 0 when
+ *             batch == 1 (blocked path for n > CI_SMALL_NMAX)
+ *   a         device, batch matrices; matrix b starts at a + b*stride
+ *   lda       leading dimension, >= n
+ *   stride    elements between matrices, >= lda*n (ignored when batch == 1)
+ *   info      device int32[batch] or NULL
+ *   work, work_bytes  scratch (size from chol_workspace_size(CI_FN_FACTOR,..))
+ * On return the upper triangle of each A holds R (real positive diagonal);
+ * the strict lower triangle is untouched.  Precision: CI_PLAIN semantics.
+ */
+int chol_factor(int dtype, int64_t batch, int64_t n, void* a, int64_t lda, int64_t stride,
+                int32_t* info, void* work, size_t work_bytes, void* stream);
+
+/*
+ * ldl_factor -- LDL factorisation in place, Section II.A eqs. (10)-(11).
+ *   Same arguments as chol_factor plus
+ *   d         device, real array (float for CI_F32/CI_C64, double otherwise)
+ *             of batch*n; matrix b's pivots at d + b*n
+ * On return the strict upper triangle of each A holds the unit upper R (its
+ * unit diagonal is implied; the diagonal of A is left as it was).  info
+ * reports the first pivot d_i that is zero or not finite (no positivity is
+ * required for the factorisation alone).  Only batched orders
+ * n <= CI_SMALL_NMAX are supported.
+ */
+int ldl_factor(int dtype, int64_t batch, int64_t n, void* a, int64_t lda, int64_t stride,
+               void* d, int32_t* info, void* stream);
+
+/*
+ * chol_inverse -- X = A^{-1} of one matrix of any order by the proposed method
+ * (Section IV): factorisation, then one back-substitution R X = S against the
+ * known upper triangle S = diag(1/r_ii) (eq. 24) or diag(1/d_i) (eq. 29) of
+ * the skipped first solve, computing only the upper half of X.
+ *   a, lda    device input (not modified)
+ *   x, ldx    device output; x may equal a only for CI_PLAIN with
+ *             n <= CI_SMALL_NMAX and lda == ldx
+ *   opts      host options (NULL = Cholesky, plain, no refinement, fill)
+ *   work      device scratch of work_bytes >= chol_workspace_size(CI_FN_INVERSE, ...)
+ *   info      device int32[1] or NULL
+ * For n > CI_SMALL_NMAX the blocked path runs: right-looking blocked Cholesky
+ * with MFMA trailing updates, then the blocked form of the Section IV
+ * back-substitution (GEMMs against the already known trailing block of X);
+ * only CI_METHOD_CHOL and real types are supported there.
+ */
+int chol_inverse(int dtype, int64_t n, const void* a, int64_t lda, void* x, int64_t ldx,
+                 const ci_opts* opts, void* work, size_t work_bytes, int32_t* info,
+                 void* stream);
+
+/*
+ * chol_inverse_batched -- X_b = A_b^{-1} for a batch of small matrices
+ * (Section IV), one matrix per lane or per lane group, in one launch.
+ *   batch       number of matrices
+ *   n_uniform   > 0: every matrix has this order (<= CI_SMALL_NMAX); matrix b
+ *               is at a + b*stride_a and x + b*stride_x, leading dimension n
+ *               0: variable orders (packed): n_dev[b] is the order of matrix b
+ *               and offsets_dev[b] its first element in both a and x; each
+ *               matrix is dense with leading dimension n_dev[b].  n_max is an
+ *               upper bound of the orders (host value, <= CI_SMALL_NMAX).
+ *   n_dev, offsets_dev  device int32[batch] / int64[batch] (varlen only)
+ *   work        device scratch (varlen: the bucketed work list lives here)
+ * Every matrix of a varlen batch is processed by the kernel of its size
+ * bucket within a single persistent launch (after a small device-side
+ * bucketing prologue), so the call is capturable in a HIP graph.
+ */
+int chol_inverse_batched(int dtype, int64_t batch, int64_t n_uniform, const int32_t* n_dev,
+                         const int64_t* offsets_dev, int64_t n_max, const void* a,
+                         int64_t stride_a, void* x, int64_t stride_x, const ci_opts* opts,
+                         void* work, size_t work_bytes, int32_t* info, void* stream);
+
+/*
+ * chol_inverse_backward -- adjoint of X = A^{-1} for the real loss
+ * L = Re<G, X> restricted to Hermitian A:  gA = -X Gh X, Gh = (G + G^H)/2.
+ * It reuses the forward's X (full Hermitian, e.g. written with fill_lower = 1)
+ * instead of recomputing the inverse.  gA is Hermitian and written in full.
+ *   x, g, ga    device, batch matrices of order n (<= CI_SMALL_NMAX), leading
+ *               dimension n, matrix b at ptr + b*stride
+ */
+int chol_inverse_backward(int dtype, int64_t batch, int64_t n, const void* x, const void* g,
+                          void* ga, int64_t stride, void* stream);
+
+/* Which entry point a workspace query is for. */
+enum { CI_FN_FACTOR = 0, CI_FN_INVERSE = 1, CI_FN_BATCHED = 2 };
+
+/* Bytes of device scratch the named entry point needs for these arguments
+ * (0 when none).  For CI_FN_BATCHED pass n = n_uniform (0 for varlen). */
+size_t chol_workspace_size(int fn, int dtype, int64_t batch, int64_t n, const ci_opts* opts);
+
+/* Human-readable text for a return code (static storage). */
+const char* chol_status_string(int code);
+
+/* Library version string (static storage). */
+const char* chol_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHOLINV_H */

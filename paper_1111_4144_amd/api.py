@@ -1,0 +1,208 @@
+"""PyTorch-facing functions over libcholinv.
+
+PyTorch provides device memory and the current HIP stream; every computation
+runs in the library's gfx950 kernels (see include/cholinv.h).  Tensors must be
+on the GPU.  Calls are asynchronous on torch's current stream unless
+``check_errors=True`` (which synchronises to read the per-matrix ``info``).
+
+* ``inverse(A, method, precision, ns_steps)``   X = A^{-1} (Section IV)
+* ``inverse_varlen(packed, sizes, offsets)``    packed batch of uneven orders
+* ``factor(A)`` / ``ldl(A)``                    Section II / II.A factorisations
+* ``inverse_backward(X, G)``                    gA = -X Gh X
+* ``CholInverse``                               autograd.Function saving X
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib as L
+
+_DT = {torch.float32: L.CI_F32, torch.float64: L.CI_F64, torch.complex64: L.CI_C64,
+       torch.complex128: L.CI_C128}
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    try:
+        return _DT[t.dtype]
+    except KeyError:
+        raise TypeError("unsupported dtype %s" % t.dtype) from None
+
+
+def _stream(device=None):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _check_device(*ts):
+    for t in ts:
+        if t is not None and not t.is_cuda:
+            raise ValueError("libcholinv operates on GPU tensors only")
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor | None:
+    if nbytes == 0:
+        return None
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+
+
+def _finish(fn, info, check_errors):
+    if check_errors and info is not None:
+        bad = torch.nonzero(info).flatten()
+        if bad.numel():
+            b = int(bad[0])
+            raise torch.linalg.LinAlgError(
+                "%s: matrix %d is not positive definite (pivot %d failed)" % (fn, b, int(info[b])))
+
+
+def inverse(A: torch.Tensor, *, method="chol", precision="plain", ns_steps=None,
+            fill_lower=True, check_errors=False, return_info=False, out=None):
+    """X = A^{-1} for Hermitian positive-definite A[..., n, n] (upper triangle read).
+
+    precision "plain": all arithmetic in A's dtype.  "mixed" (float32 /
+    complex64 only): FP32 bulk, FP64 pivots, then ``ns_steps`` (default 1)
+    Newton-Schulz steps with an FP64 residual.
+    """
+    _check_device(A)
+    if A.dim() < 2 or A.shape[-1] != A.shape[-2]:
+        raise ValueError("A must be [..., n, n]")
+    if ns_steps is None:
+        ns_steps = 1 if precision == "mixed" else 0
+    n = A.shape[-1]
+    batch_shape = A.shape[:-2]
+    A3 = A.reshape(-1, n, n)
+    if not A3.is_contiguous():
+        A3 = A3.contiguous()
+    B = A3.shape[0]
+    X = out if out is not None else torch.empty_like(A3)
+    if out is not None:
+        _check_device(out)
+        if out.shape != A3.shape or not out.is_contiguous() or out.dtype != A.dtype:
+            raise ValueError("out must be a contiguous tensor shaped like A")
+    info = torch.zeros(B, dtype=torch.int32, device=A.device)
+    opts = L.make_opts(method, precision, ns_steps, fill_lower)
+    dt = _dtype_code(A)
+    lib = L.lib()
+    s = _stream(A.device)
+    if n <= L.CI_SMALL_NMAX:
+        rc = lib.chol_inverse_batched(dt, B, n, None, None, 0, _ptr(A3), n * n, _ptr(X), n * n,
+                                      ctypes.byref(opts), None, 0, _ptr(info), s)
+        L.check("chol_inverse_batched", rc)
+    else:
+        ws = lib.chol_workspace_size(L.CI_FN_INVERSE, dt, 1, n, ctypes.byref(opts))
+        work = _workspace(ws, A.device)
+        for b in range(B):
+            rc = lib.chol_inverse(dt, n, _ptr(A3[b]), n, _ptr(X[b]), n, ctypes.byref(opts),
+                                  _ptr(work), ws, _ptr(info[b:b + 1]), s)
+            L.check("chol_inverse", rc)
+    _finish("inverse", info, check_errors)
+    X = X.reshape(*batch_shape, n, n)
+    info = info.reshape(batch_shape)
+    return (X, info) if return_info else X
+
+
+def inverse_varlen(packed: torch.Tensor, sizes: torch.Tensor, offsets: torch.Tensor, *,
+                   n_max: int | None = None, method="chol", precision="plain", ns_steps=None,
+                   fill_lower=True, out=None, check_errors=False, return_info=False,
+                   workspace: torch.Tensor | None = None):
+    """Inverse of every matrix of a packed batch: matrix b has order sizes[b] and
+    starts at element offsets[b] (dense, leading dimension sizes[b])."""
+    _check_device(packed, sizes, offsets)
+    if ns_steps is None:
+        ns_steps = 1 if precision == "mixed" else 0
+    sizes = sizes.to(torch.int32).contiguous()
+    offsets = offsets.to(torch.int64).contiguous()
+    B = sizes.shape[0]
+    if n_max is None:
+        n_max = int(sizes.max()) if B else 1
+    X = out if out is not None else torch.empty_like(packed)
+    info = torch.zeros(B, dtype=torch.int32, device=packed.device)
+    opts = L.make_opts(method, precision, ns_steps, fill_lower)
+    lib = L.lib()
+    dt = _dtype_code(packed)
+    ws = lib.chol_workspace_size(L.CI_FN_BATCHED, dt, B, 0, ctypes.byref(opts))
+    if workspace is None or workspace.numel() < ws:
+        workspace = _workspace(ws, packed.device)
+    rc = lib.chol_inverse_batched(dt, B, 0, _ptr(sizes), _ptr(offsets), int(n_max), _ptr(packed),
+                                  0, _ptr(X), 0, ctypes.byref(opts), _ptr(workspace), ws,
+                                  _ptr(info), _stream(packed.device))
+    L.check("chol_inverse_batched", rc)
+    _finish("inverse_varlen", info, check_errors)
+    return (X, info) if return_info else X
+
+
+def factor(A: torch.Tensor, *, inplace=False, return_info=False):
+    """Cholesky factor R (upper, A = R^* R, eqs. 3-4) of A[..., n, n]; the strict
+    lower triangle is copied from A unchanged."""
+    _check_device(A)
+    n = A.shape[-1]
+    R = A if inplace else A.clone()
+    R3 = R.reshape(-1, n, n)
+    B = R3.shape[0]
+    info = torch.zeros(B, dtype=torch.int32, device=A.device)
+    lib = L.lib()
+    dt = _dtype_code(A)
+    if n <= L.CI_SMALL_NMAX:
+        rc = lib.chol_factor(dt, B, n, _ptr(R3), n, n * n, _ptr(info), None, 0, _stream(A.device))
+        L.check("chol_factor", rc)
+    else:
+        ws = lib.chol_workspace_size(L.CI_FN_FACTOR, dt, 1, n, None)
+        work = _workspace(ws, A.device)
+        for b in range(B):
+            rc = lib.chol_factor(dt, 1, n, _ptr(R3[b]), n, n * n, _ptr(info[b:b + 1]),
+                                 _ptr(work), ws, _stream(A.device))
+            L.check("chol_factor", rc)
+    return (R, info.reshape(A.shape[:-2])) if return_info else R
+
+
+def ldl(A: torch.Tensor, *, return_info=False):
+    """LDL factors (R unit upper in the strict upper triangle, d) of A[..., n, n]
+    (eqs. 10-11).  Returns (R_with_A's_diagonal_and_lower, d)."""
+    _check_device(A)
+    n = A.shape[-1]
+    R = A.clone()
+    R3 = R.reshape(-1, n, n)
+    B = R3.shape[0]
+    rdt = torch.float32 if A.dtype in (torch.float32, torch.complex64) else torch.float64
+    d = torch.empty(B, n, dtype=rdt, device=A.device)
+    info = torch.zeros(B, dtype=torch.int32, device=A.device)
+    rc = L.lib().ldl_factor(_dtype_code(A), B, n, _ptr(R3), n, n * n, _ptr(d), _ptr(info),
+                            _stream(A.device))
+    L.check("ldl_factor", rc)
+    d = d.reshape(*A.shape[:-2], n)
+    return (R, d, info.reshape(A.shape[:-2])) if return_info else (R, d)
+
+
+def inverse_backward(X: torch.Tensor, G: torch.Tensor) -> torch.Tensor:
+    """gA = -X Gh X, Gh = (G + G^H)/2, from the forward's full Hermitian X."""
+    _check_device(X, G)
+    n = X.shape[-1]
+    X3 = X.reshape(-1, n, n).contiguous()
+    G3 = G.reshape(-1, n, n).to(X.dtype).contiguous()
+    gA = torch.empty_like(X3)
+    rc = L.lib().chol_inverse_backward(_dtype_code(X), X3.shape[0], n, _ptr(X3), _ptr(G3),
+                                       _ptr(gA), n * n, _stream(X.device))
+    L.check("chol_inverse_backward", rc)
+    return gA.reshape(X.shape)
+
+
+class CholInverse(torch.autograd.Function):
+    """X = A^{-1} with the hand-written adjoint; the backward reuses the saved X.
+
+    The gradient is the Hermitian one, gA = -X Gh X, i.e. the gradient of the
+    real loss along Hermitian perturbations of A (the domain of the method)."""
+
+    @staticmethod
+    def forward(ctx, A, method="chol", precision="plain", ns_steps=None):
+        X = inverse(A, method=method, precision=precision, ns_steps=ns_steps, fill_lower=True)
+        ctx.save_for_backward(X)
+        return X
+
+    @staticmethod
+    def backward(ctx, G):
+        (X,) = ctx.saved_tensors
+        return inverse_backward(X, G), None, None, None

@@ -1,0 +1,213 @@
+// abi.cpp -- the C-ABI of libcholinv (declared in include/cholinv.h):
+// argument checks, dispatch to the kernel families, error mapping.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+
+#include "ci_launch.hpp"
+#include "ci_large.hpp"
+#include "cholinv.h"
+
+namespace {
+
+int map_err(hipError_t e)
+{
+    if (e == hipSuccess) return 0;
+    if (e == hipErrorNotSupported) return CI_ERR_UNSUPPORTED;
+    return CI_ERR_LAUNCH - (int)e;
+}
+
+bool valid_dtype(int d) { return d >= CI_F32 && d <= CI_C128; }
+
+bool is_f32(int d) { return d == CI_F32 || d == CI_C64; }
+
+size_t elem_size(int d)
+{
+    switch (d) {
+    case CI_F32: return 4;
+    case CI_F64: return 8;
+    case CI_C64: return 8;
+    case CI_C128: return 16;
+    default: return 0;
+    }
+}
+
+ci_opts default_opts() { return ci_opts{CI_METHOD_CHOL, CI_PLAIN, 0, 1}; }
+
+// Returns 0 or the negative index (relative to `base`) of the bad option.
+int check_opts(const ci_opts& o, int dtype)
+{
+    if (o.method != CI_METHOD_CHOL && o.method != CI_METHOD_LDL) return 1;
+    if (o.precision != CI_PLAIN && o.precision != CI_MIXED) return 1;
+    if (o.precision == CI_MIXED && !is_f32(dtype)) return 1;
+    if (o.ns_steps < 0 || o.ns_steps > 3) return 1;
+    if (o.precision == CI_PLAIN && o.ns_steps != 0) return 1;
+    if (o.fill_lower != 0 && o.fill_lower != 1) return 1;
+    return 0;
+}
+
+hipError_t run_small(int dtype, int64_t n, int op, int method, int mixed, const ci::BatchArgs& p,
+                     hipStream_t s)
+{
+    if (n <= ci::tpm_nmax(dtype, mixed)) return ci::launch_tpm(dtype, (int)n, op, method, mixed, p, s);
+    return ci::launch_group(dtype, (int)n, op, method, mixed, p, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int chol_factor(int dtype, int64_t batch, int64_t n, void* a, int64_t lda, int64_t stride,
+                int32_t* info, void* work, size_t work_bytes, void* stream)
+{
+    if (!valid_dtype(dtype)) return -1;
+    if (batch < 0) return -2;
+    if (n < 0 || (batch > 1 && n > CI_SMALL_NMAX)) return -3;
+    if (batch > 0 && n > 0 && !a) return -4;
+    if (lda < std::max<int64_t>(1, n)) return -5;
+    if (batch > 1 && stride < lda * n) return -6;
+    hipStream_t s = (hipStream_t)stream;
+    if (batch == 0) return 0;
+    if (n == 0) return info ? map_err(ci::fill_i32(info, batch, 0, s)) : 0;
+    if (n > CI_SMALL_NMAX) {
+        size_t need = ci::large_workspace(dtype, n, ci::LG_FACTOR, 0);
+        if (work_bytes < need || (need && !work)) return CI_ERR_WORKSPACE;
+        return map_err(ci::large_factor(dtype, n, a, lda, info, work, s));
+    }
+    ci::BatchArgs p{a, a, batch, lda, batch > 1 ? stride : lda * n, lda,
+                    batch > 1 ? stride : lda * n, 0, 0, info, nullptr};
+    return map_err(run_small(dtype, n, ci::OP_CHOL_FACTOR, 0, 0, p, s));
+}
+
+int ldl_factor(int dtype, int64_t batch, int64_t n, void* a, int64_t lda, int64_t stride,
+               void* d, int32_t* info, void* stream)
+{
+    if (!valid_dtype(dtype)) return -1;
+    if (batch < 0) return -2;
+    if (n < 0 || n > CI_SMALL_NMAX) return -3;
+    if (batch > 0 && n > 0 && !a) return -4;
+    if (lda < std::max<int64_t>(1, n)) return -5;
+    if (batch > 1 && stride < lda * n) return -6;
+    if (batch > 0 && n > 0 && !d) return -7;
+    hipStream_t s = (hipStream_t)stream;
+    if (batch == 0) return 0;
+    if (n == 0) return info ? map_err(ci::fill_i32(info, batch, 0, s)) : 0;
+    ci::BatchArgs p{a, a, batch, lda, batch > 1 ? stride : lda * n, lda,
+                    batch > 1 ? stride : lda * n, 0, 0, info, d};
+    return map_err(run_small(dtype, n, ci::OP_LDL_FACTOR, 1, 0, p, s));
+}
+
+int chol_inverse(int dtype, int64_t n, const void* a, int64_t lda, void* x, int64_t ldx,
+                 const ci_opts* opts, void* work, size_t work_bytes, int32_t* info, void* stream)
+{
+    if (!valid_dtype(dtype)) return -1;
+    if (n < 0) return -2;
+    if (n > 0 && !a) return -3;
+    if (lda < std::max<int64_t>(1, n)) return -4;
+    if (n > 0 && !x) return -5;
+    if (ldx < std::max<int64_t>(1, n)) return -6;
+    ci_opts o = opts ? *opts : default_opts();
+    if (check_opts(o, dtype)) return -7;
+    hipStream_t s = (hipStream_t)stream;
+    if (n == 0) return info ? map_err(ci::fill_i32(info, 1, 0, s)) : 0;
+    if (n > CI_SMALL_NMAX) {
+        if (a == x) return -5;
+        size_t need = ci::large_workspace(dtype, n, ci::LG_INVERSE, o.precision == CI_MIXED);
+        if (work_bytes < need || (need && !work)) return CI_ERR_WORKSPACE;
+        if (o.method != CI_METHOD_CHOL) return CI_ERR_UNSUPPORTED;
+        return map_err(ci::large_inverse(dtype, n, a, lda, x, ldx, o.precision == CI_MIXED,
+                                         o.ns_steps, o.fill_lower, info, work, s));
+    }
+    if (a == x && (o.precision == CI_MIXED || lda != ldx)) return -5;
+    ci::BatchArgs p{a, x, 1, lda, lda * n, ldx, ldx * n, o.ns_steps, o.fill_lower, info, nullptr};
+    return map_err(run_small(dtype, n, ci::OP_INV, o.method, o.precision == CI_MIXED, p, s));
+}
+
+int chol_inverse_batched(int dtype, int64_t batch, int64_t n_uniform, const int32_t* n_dev,
+                         const int64_t* offsets_dev, int64_t n_max, const void* a,
+                         int64_t stride_a, void* x, int64_t stride_x, const ci_opts* opts,
+                         void* work, size_t work_bytes, int32_t* info, void* stream)
+{
+    if (!valid_dtype(dtype)) return -1;
+    if (batch < 0) return -2;
+    if (n_uniform < 0 || n_uniform > CI_SMALL_NMAX) return -3;
+    const bool varlen = n_uniform == 0;
+    if (varlen && batch > 0 && !n_dev) return -4;
+    if (varlen && batch > 0 && !offsets_dev) return -5;
+    if (varlen && (n_max < 1 || n_max > CI_SMALL_NMAX)) return -6;
+    if (batch > 0 && !a) return -7;
+    if (!varlen && stride_a < n_uniform * n_uniform) return -8;
+    if (batch > 0 && !x) return -9;
+    if (!varlen && stride_x < n_uniform * n_uniform) return -10;
+    ci_opts o = opts ? *opts : default_opts();
+    if (check_opts(o, dtype)) return -11;
+    hipStream_t s = (hipStream_t)stream;
+    if (batch == 0) return 0;
+    if (a == x && o.precision == CI_MIXED) return -9;
+    if (varlen) {
+        size_t need = ci::varlen_workspace(batch);
+        if (work_bytes < need || !work) return CI_ERR_WORKSPACE;
+        return map_err(ci::launch_varlen(dtype, batch, n_dev, offsets_dev, (int)n_max, a, x,
+                                         o.method, o.precision == CI_MIXED, o.ns_steps,
+                                         o.fill_lower, info, work, s));
+    }
+    ci::BatchArgs p{a, x, batch, n_uniform, stride_a, n_uniform, stride_x, o.ns_steps,
+                    o.fill_lower, info, nullptr};
+    return map_err(run_small(dtype, n_uniform, ci::OP_INV, o.method, o.precision == CI_MIXED, p, s));
+}
+
+int chol_inverse_backward(int dtype, int64_t batch, int64_t n, const void* x, const void* g,
+                          void* ga, int64_t stride, void* stream)
+{
+    if (!valid_dtype(dtype)) return -1;
+    if (batch < 0) return -2;
+    if (n < 0 || n > CI_SMALL_NMAX) return -3;
+    if (batch > 0 && n > 0 && !x) return -4;
+    if (batch > 0 && n > 0 && !g) return -5;
+    if (batch > 0 && n > 0 && !ga) return -6;
+    if (stride < n * n) return -7;
+    if (batch == 0 || n == 0) return 0;
+    return map_err(ci::launch_backward(dtype, (int)n, x, g, ga, batch, stride, (hipStream_t)stream));
+}
+
+size_t chol_workspace_size(int fn, int dtype, int64_t batch, int64_t n, const ci_opts* opts)
+{
+    if (!valid_dtype(dtype) || batch < 0 || n < 0) return 0;
+    ci_opts o = opts ? *opts : default_opts();
+    switch (fn) {
+    case CI_FN_FACTOR:
+        return (batch <= 1 && n > CI_SMALL_NMAX) ? ci::large_workspace(dtype, n, ci::LG_FACTOR, 0)
+                                                 : 0;
+    case CI_FN_INVERSE:
+        return n > CI_SMALL_NMAX
+                   ? ci::large_workspace(dtype, n, ci::LG_INVERSE, o.precision == CI_MIXED)
+                   : 0;
+    case CI_FN_BATCHED:
+        return n == 0 ? ci::varlen_workspace(batch) : 0;
+    default:
+        return 0;
+    }
+}
+
+const char* chol_status_string(int code)
+{
+    static thread_local char buf[96];
+    if (code == 0) return "success";
+    if (code == CI_ERR_UNSUPPORTED) return "unsupported combination of arguments";
+    if (code == CI_ERR_WORKSPACE) return "workspace too small";
+    if (code <= CI_ERR_LAUNCH && code > CI_ERR_LAUNCH - 1000) {
+        std::snprintf(buf, sizeof buf, "HIP launch error %d (%s)", CI_ERR_LAUNCH - code,
+                      hipGetErrorString((hipError_t)(CI_ERR_LAUNCH - code)));
+        return buf;
+    }
+    if (code < 0 && code > -100) {
+        std::snprintf(buf, sizeof buf, "argument %d is invalid", -code);
+        return buf;
+    }
+    return "unknown status";
+}
+
+const char* chol_version(void) { return "cholinv 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,64 @@
+// ci_launch.hpp -- host-side launchers of the gfx950 kernels (internal to
+// libcholinv; the public interface is include/cholinv.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ci {
+
+enum { OP_INV = 0, OP_CHOL_FACTOR = 1, OP_LDL_FACTOR = 2 };
+enum { DT_F32 = 0, DT_F64 = 1, DT_C64 = 2, DT_C128 = 3 };
+
+// Thread-per-matrix kernels: one lane owns one whole matrix in registers.
+// Compiled for orders 1..TPM_NMAX_REAL (real) and 1..TPM_NMAX_CPLX (complex);
+// tpm_nmax() is the largest order dispatched to them (beyond it the register
+// footprint of one matrix per lane costs more than lane groups do).
+constexpr int TPM_NMAX_REAL = 16;
+constexpr int TPM_NMAX_CPLX = 8;
+constexpr int TPM_BLOCK = 64;
+
+// Kernel variant request (autotuner / tests): 0 = automatic, 1 = load each
+// lane's matrix directly from HBM, 2 = one-shot LDS staging, 3 = persistent
+// pipelined LDS staging.
+enum { VARIANT_AUTO = 0, VARIANT_DIRECT = 1, VARIANT_STAGED = 2, VARIANT_PERSIST = 3 };
+
+// Compute units of the current device (cached).
+int device_cus();
+
+struct BatchArgs {
+    const void* a;
+    void* x;
+    int64_t batch, lda, sa, ldx, sx;
+    int ns_steps;
+    int fill;
+    int32_t* info;
+    void* dout;        // LDL pivots (OP_LDL_FACTOR)
+    int variant = VARIANT_AUTO;
+};
+
+int tpm_nmax(int dtype, int mixed);
+
+// Process-wide default variant (environment CHOLINV_TPM_VARIANT=direct|staged,
+// read once; set by the tuner).
+int tpm_default_variant();
+void tpm_set_default_variant(int v);
+
+// Returns a hipError_t (hipSuccess or the launch error); hipErrorNotSupported
+// when no kernel exists for the combination.
+hipError_t launch_tpm(int dtype, int n, int op, int method, int mixed, const BatchArgs& p,
+                      hipStream_t s);
+hipError_t launch_tpm_f32(int n, int op, int method, int mixed, const BatchArgs& p, hipStream_t s);
+hipError_t launch_tpm_f64(int n, int op, int method, int mixed, const BatchArgs& p, hipStream_t s);
+hipError_t launch_tpm_c64(int n, int op, int method, int mixed, const BatchArgs& p, hipStream_t s);
+hipError_t launch_tpm_c128(int n, int op, int method, int mixed, const BatchArgs& p, hipStream_t s);
+
+// Group-per-matrix kernels (TPM_NMAX < n <= 64, and the varlen buckets).
+hipError_t launch_group(int dtype, int n, int op, int method, int mixed, const BatchArgs& p,
+                        hipStream_t s);
+
+// Backward gA = -X Gh X.
+hipError_t launch_backward(int dtype, int n, const void* x, const void* g, void* ga,
+                           int64_t batch, int64_t stride, hipStream_t s);
+
+}  // namespace ci

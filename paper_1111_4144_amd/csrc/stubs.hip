@@ -1,0 +1,36 @@
+// stubs.hip -- entry points whose kernels are not built yet.
+#include "ci_large.hpp"
+#include "ci_launch.hpp"
+
+namespace ci {
+
+__global__ void k_fill_i32(int32_t* p, int64_t count, int32_t v)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+hipError_t fill_i32(int32_t* p, int64_t count, int32_t value, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, count,
+                       value);
+    return hipGetLastError();
+}
+
+size_t large_workspace(int, int64_t, int, int) { return 0; }
+hipError_t large_factor(int, int64_t, void*, int64_t, int32_t*, void*, hipStream_t)
+{ return hipErrorNotSupported; }
+hipError_t large_inverse(int, int64_t, const void*, int64_t, void*, int64_t, int, int, int,
+                         int32_t*, void*, hipStream_t)
+{ return hipErrorNotSupported; }
+size_t varlen_workspace(int64_t) { return 0; }
+hipError_t launch_varlen(int, int64_t, const int32_t*, const int64_t*, int, const void*, void*,
+                         int, int, int, int, int32_t*, void*, hipStream_t)
+{ return hipErrorNotSupported; }
+hipError_t launch_group(int, int, int, int, int, const BatchArgs&, hipStream_t)
+{ return hipErrorNotSupported; }
+hipError_t launch_backward(int, int, const void*, const void*, void*, int64_t, int64_t, hipStream_t)
+{ return hipErrorNotSupported; }
+
+}  // namespace ci
