@@ -30,6 +30,7 @@ CXXFLAGS = [
     "-x", "hip", "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
     "-I" + INCLUDE, "-I" + CSRC,
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-mllvm", "-pragma-unroll-threshold=1000000",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unknown-warning-option",
 ]
 

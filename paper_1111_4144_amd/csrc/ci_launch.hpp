@@ -35,6 +35,7 @@ struct BatchArgs {
     int32_t* info;
     void* dout;        // LDL pivots (OP_LDL_FACTOR)
     int variant = VARIANT_AUTO;
+    int group = 0;     // lanes per matrix for the group kernels (0 = default)
 };
 
 int tpm_nmax(int dtype, int mixed);
@@ -53,9 +54,19 @@ hipError_t launch_tpm_f64(int n, int op, int method, int mixed, const BatchArgs&
 hipError_t launch_tpm_c64(int n, int op, int method, int mixed, const BatchArgs& p, hipStream_t s);
 hipError_t launch_tpm_c128(int n, int op, int method, int mixed, const BatchArgs& p, hipStream_t s);
 
-// Group-per-matrix kernels (TPM_NMAX < n <= 64, and the varlen buckets).
+// Group-per-matrix kernels (orders above tpm_nmax, up to 64 for real and 32
+// for complex elements).
 hipError_t launch_group(int dtype, int n, int op, int method, int mixed, const BatchArgs& p,
                         hipStream_t s);
+hipError_t launch_group_f32(int n, int op, int method, int mixed, const BatchArgs& p, hipStream_t s);
+hipError_t launch_group_f64(int n, int op, int method, int mixed, const BatchArgs& p, hipStream_t s);
+hipError_t launch_group_c64(int n, int op, int method, int mixed, const BatchArgs& p, hipStream_t s);
+hipError_t launch_group_c128(int n, int op, int method, int mixed, const BatchArgs& p, hipStream_t s);
+// LDS-resident group kernels for orders 17..64 (real) / 17..32 (complex).
+hipError_t launch_wpm_f32(int n, int op, int method, int mixed, const BatchArgs& p, hipStream_t s);
+hipError_t launch_wpm_f64(int n, int op, int method, int mixed, const BatchArgs& p, hipStream_t s);
+hipError_t launch_wpm_c64(int n, int op, int method, int mixed, const BatchArgs& p, hipStream_t s);
+hipError_t launch_wpm_c128(int n, int op, int method, int mixed, const BatchArgs& p, hipStream_t s);
 
 // Backward gA = -X Gh X.
 hipError_t launch_backward(int dtype, int n, const void* x, const void* g, void* ga,

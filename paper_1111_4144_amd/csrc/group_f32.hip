@@ -1,0 +1,13 @@
+// group_f32.hip -- register lane-group kernels (orders up to 16) for float elements.
+#include "group_impl.hpp"
+
+namespace ci {
+
+hipError_t launch_group_f32(int n, int op, int method, int mixed, const BatchArgs& p,
+                              hipStream_t s)
+{
+    if (n <= 16) return group_run_ops<float, 16, 16>(n, op, method, mixed, p, s);
+    return launch_wpm_f32(n, op, method, mixed, p, s);
+}
+
+}  // namespace ci

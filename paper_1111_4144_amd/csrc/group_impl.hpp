@@ -1,0 +1,388 @@
+// group_impl.hpp -- batched small-matrix kernels, G lanes per matrix.
+// Included by one translation unit per element type.
+//
+// The G lanes of a group share one matrix of order n <= NB (a padded bucket:
+// entries beyond n are those of the identity, which changes no entry of the
+// n x n result).  Columns are dealt cyclically: lane q owns columns
+// j = s*G + q (slot s).  Each lane keeps, per owned column, one register
+// array M[s][0..NB) that holds
+//   * during the factorisation: column j of the partly reduced A, whose
+//     entries k <= j become column j of R (right-looking form of eqs. 3-4 or
+//     10-11; the FP64 / compute-precision pivot accumulator is separate);
+//   * during the Section IV back-substitution, which runs over rows
+//     i = NB-1 .. 0: entries k < i still hold R, entries k >= i hold column j
+//     of the Hermitian X-hat (x_kj for k <= j, conj(x_jk) for k > j).  Row i of
+//     R dies exactly when row i of X is born, so R and X share the storage.
+// Row i of R is broadcast from its owners with cross-lane moves inside the
+// group (DPP quad_perm / row_newbcast, ds_swizzle or readlane by G).
+// Mixed precision keeps column j of A (full Hermitian) for the Newton-Schulz
+// residual E = I - A X, accumulated in FP64 one k at a time.
+#pragma once
+
+#include <utility>
+
+#include "ci_launch.hpp"
+#include "ci_types.hpp"
+
+namespace ci {
+
+// ---- cross-lane broadcast inside a group of G lanes ---------------------------
+template <int G, int K>
+CI_D int bc32_k(int v)
+{
+    static_assert(K >= 0 && K < G, "source lane inside the group");
+    if constexpr (G == 1) {
+        return v;
+    } else if constexpr (G == 2) {
+        return __builtin_amdgcn_mov_dpp(v, K | (K << 2) | ((K + 2) << 4) | ((K + 2) << 6), 0xf,
+                                        0xf, false);
+    } else if constexpr (G == 4) {
+        return __builtin_amdgcn_mov_dpp(v, K | (K << 2) | (K << 4) | (K << 6), 0xf, 0xf, false);
+    } else if constexpr (G == 8) {
+        // ds_swizzle bit mode: lane' = (lane & 0b11000) | K inside each 32 lanes
+        return __builtin_amdgcn_ds_swizzle(v, 0x18 | (K << 5));
+    } else if constexpr (G == 16) {
+        return __builtin_amdgcn_mov_dpp(v, 0x150 + K, 0xf, 0xf, false);   // row_newbcast:K
+    } else if constexpr (G == 32) {
+        return __builtin_amdgcn_ds_swizzle(v, K << 5);                   // lane' = K
+    } else {
+        static_assert(G == 64, "group size");
+        return __builtin_amdgcn_readlane(v, K);
+    }
+}
+
+template <int G, int... Ks>
+CI_D int bc32_dispatch(int v, int k, std::integer_sequence<int, Ks...>)
+{
+    int r = v;
+    ((k == Ks ? (r = bc32_k<G, Ks>(v), 0) : 0), ...);
+    return r;
+}
+
+// k must fold to a constant (every caller sits in fully unrolled loops).
+template <int G>
+CI_D int bc32(int v, int k)
+{
+    return bc32_dispatch<G>(v, k, std::make_integer_sequence<int, G>{});
+}
+
+template <int G> CI_D float bc(float v, int k) { return __builtin_bit_cast(float, bc32<G>(__builtin_bit_cast(int, v), k)); }
+template <int G> CI_D double bc(double v, int k) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const int lo = bc32<G>((int)(uint32_t)u, k), hi = bc32<G>((int)(uint32_t)(u >> 32), k);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+template <int G> CI_D cf bc(cf v, int k) { return cf{bc<G>(v.re, k), bc<G>(v.im, k)}; }
+template <int G> CI_D cd bc(cd v, int k) { return cd{bc<G>(v.re, k), bc<G>(v.im, k)}; }
+template <int G> CI_D int bci(int v, int k) { return bc32<G>(v, k); }
+
+// Broadcast from a run-time source lane k of the group (k uniform across the
+// wave): readlane for whole-wave groups, ds_bpermute otherwise.
+template <int G>
+CI_D int bcr32(int v, int k)
+{
+    if constexpr (G == 1) {
+        return v;
+    } else if constexpr (G == 64) {
+        return __builtin_amdgcn_readlane(v, k);
+    } else {
+        const int src = ((int)(threadIdx.x & 63) & ~(G - 1)) | k;
+        return __builtin_amdgcn_ds_bpermute(src << 2, v);
+    }
+}
+template <int G> CI_D float bcr(float v, int k) { return __builtin_bit_cast(float, bcr32<G>(__builtin_bit_cast(int, v), k)); }
+template <int G> CI_D double bcr(double v, int k) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const int lo = bcr32<G>((int)(uint32_t)u, k), hi = bcr32<G>((int)(uint32_t)(u >> 32), k);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+template <int G> CI_D cf bcr(cf v, int k) { return cf{bcr<G>(v.re, k), bcr<G>(v.im, k)}; }
+template <int G> CI_D cd bcr(cd v, int k) { return cd{bcr<G>(v.re, k), bcr<G>(v.im, k)}; }
+
+template <class V>
+CI_D V sel(bool c, V a, V b) { return c ? a : b; }
+
+// re(conj(a) b) in precision P (products of FP32 values are exact in FP64)
+template <class P> CI_D P dot_re(float a, float b) { return (P)a * (P)b; }
+template <class P> CI_D P dot_re(double a, double b) { return (P)(a * b); }
+template <class P> CI_D P dot_re(cf a, cf b) { return (P)a.re * (P)b.re + (P)a.im * (P)b.im; }
+template <class P> CI_D P dot_re(cd a, cd b) { return (P)(a.re * b.re + a.im * b.im); }
+
+// ---- one matrix per group ------------------------------------------------------
+// All G lanes of the group call this together (valid or not: the cross-lane
+// moves need every lane); `valid` only gates memory accesses.
+template <class V, int NB, int G, int OP, int METHOD, int MIXED>
+CI_D void group_matrix(const V* __restrict__ a, int64_t lda, int n, V* x, int64_t ldx, bool valid,
+                       int fill, int ns_steps, int q, int32_t* info_b,
+                       typename vt<V>::real* dout_b)
+{
+    using R = typename vt<V>::real;
+    using W = typename vt<V>::wide;
+    using P = typename std::conditional<MIXED, double, R>::type;   // pivot precision
+    constexpr int S = (NB + G - 1) / G;                             // slots per lane
+
+    V M[S][NB];
+    V Af[MIXED ? S : 1][MIXED ? NB : 1];
+    P piv[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) piv[s] = P(1);
+    // ---- load column j = s*G + q (upper part from column j, lower part from
+    // row j, i.e. only the upper triangle of A is read); identity padding
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int j = s * G + q;
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            V v = mk<V>(R(k == j ? 1 : 0));
+            if (valid && j < n && k < n) {
+                v = (k <= j) ? a[k * lda + j] : cj(a[j * lda + k]);
+                if (k == j) v = realpart_only(v);
+            }
+            if constexpr (MIXED) Af[s][k] = v;
+            M[s][k] = (k <= j) ? v : mk<V>(R(0));
+            if (k == j) piv[s] = (P)re(v);
+        }
+    }
+
+    // ---- factorisation, right-looking ----------------------------------------
+    int fail = 0;
+    R sall[NB];     // 1/r_ii or 1/d_i, broadcast to every lane
+    R dall[NB];     // LDL pivots
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int qi = i % G, si = i / G;
+        // pivot on the owner of column i
+        const P pv = piv[si];
+        bool ok;
+        R rdiag, sinv, dval;
+        if constexpr (METHOD == 0) {
+            ok = pivot_ok(pv);
+            const P r = sqrt(pv);
+            rdiag = (R)r;
+            sinv = (R)(P(1) / r);
+            dval = rdiag;
+        } else {
+            ok = (OP == OP_LDL_FACTOR) ? (pv != P(0) && pv - pv == P(0)) : pivot_ok(pv);
+            dval = (R)pv;
+            sinv = (R)(P(1) / pv);
+            rdiag = R(1);
+        }
+        const int okb = bci<G>(ok ? 1 : 0, qi);
+        if (!okb && !fail) fail = i + 1;
+        sinv = bc<G>(sinv, qi);
+        dval = bc<G>(dval, qi);
+        sall[i] = sinv;
+        dall[i] = dval;
+        // row i of R on every owned column j > i.  The trailing update takes
+        // w_ij = r_ij (Cholesky) or the unscaled u_ij = d_i r_ij (LDL):
+        //   a_kj -= conj(r_ik) w_ij,   pivot_j -= re(conj(r_ij) w_ij)
+        V wv[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int j = s * G + q;
+            const V u = M[s][i];
+            const V r = scal(u, sinv);
+            wv[s] = (METHOD == 0) ? r : u;
+            M[s][i] = (j > i) ? r : ((j == i) ? mk<V>(rdiag) : M[s][i]);
+            const P dlt = dot_re<P>(r, wv[s]);
+            piv[s] = (j > i) ? piv[s] - dlt : piv[s];
+        }
+#pragma unroll
+        for (int k = i + 1; k < NB; ++k) {
+            const V rik = bc<G>(M[k / G][i], k % G);
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                if (s * G + G - 1 >= k) msubc(M[s][k], rik, wv[s]);
+            }
+        }
+    }
+
+    if constexpr (OP == OP_CHOL_FACTOR || OP == OP_LDL_FACTOR) {
+        constexpr int J0 = (OP == OP_LDL_FACTOR) ? 1 : 0;
+        if (valid) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int j = s * G + q;
+                if (j < n) {
+#pragma unroll
+                    for (int k = 0; k < NB; ++k)
+                        if (k + J0 <= j && k < n) x[k * ldx + j] = M[s][k];
+                }
+            }
+            if constexpr (OP == OP_LDL_FACTOR) {
+#pragma unroll
+                for (int i = 0; i < NB; ++i)
+                    if (i % G == q && i < n) dout_b[i] = dall[i];
+            }
+        }
+    } else {
+        // ---- Section IV: rows i = NB-1 .. 0 of R X = S ------------------------
+#pragma unroll
+        for (int i = NB - 1; i >= 0; --i) {
+            const int qi = i % G, si = i / G;
+            // (a) x_ij, j > i: -s_i sum_{k>i} r_ik xh_kj (chol) or without s_i (LDL)
+            V acc[S];
+#pragma unroll
+            for (int s = 0; s < S; ++s) acc[s] = mk<V>(R(0));
+#pragma unroll
+            for (int k = i + 1; k < NB; ++k) {
+                const V rik = bc<G>(M[k / G][i], k % G);
+#pragma unroll
+                for (int s = 0; s < S; ++s) msub(acc[s], rik, M[s][k]);
+            }
+            V xnew[S];
+#pragma unroll
+            for (int s = 0; s < S; ++s) xnew[s] = (METHOD == 0) ? scal(acc[s], sall[i]) : acc[s];
+            // (b) deliver conj(x_ij), j > i, into column i (owner qi, slot si)
+#pragma unroll
+            for (int j = i + 1; j < NB; ++j) {
+                const V v = bc<G>(xnew[j / G], j % G);
+                M[si][j] = (q == qi) ? cj(v) : M[si][j];
+            }
+            // (c) x_ii = s_i (s_i - sum_{k>i} r_ik conj(x_ik)) on the owner; row i
+            // of R is still in place (it is replaced only below)
+            V d = mk<V>(sall[i]);
+#pragma unroll
+            for (int k = i + 1; k < NB; ++k) {
+                const V rik = bc<G>(M[k / G][i], k % G);
+                msub(d, rik, M[si][k]);
+            }
+            d = realpart_only((METHOD == 0) ? scal(d, sall[i]) : d);
+            // row i of X replaces row i of R
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int j = s * G + q;
+                M[s][i] = (j > i) ? xnew[s] : ((j == i) ? d : M[s][i]);
+            }
+        }
+
+        // ---- Newton-Schulz: X <- X + X(I - A X), residual in FP64 -------------
+        // For every k: e_kj = delta_kj - sum_m a_km xh_mj (FP64, column k of A
+        // from its owner; a_km = conj(a_mk)), then X E accumulates
+        // upd_ij += xh_ik e_kj for all i (column k of X-hat from its owner).
+        if (MIXED && ns_steps > 0) {
+            for (int step = 0; step < ns_steps; ++step) {
+                V upd[S][NB];
+#pragma unroll
+                for (int s = 0; s < S; ++s)
+#pragma unroll
+                    for (int i = 0; i < NB; ++i) upd[s][i] = M[s][i];
+                if constexpr (S == 1) {
+                    // one column per lane: the source lane of column k is k itself,
+                    // so k can stay a run-time loop (code size NB^2, not NB^3)
+#pragma unroll 1
+                    for (int k = 0; k < NB; ++k) {
+                        W e = widen(mk<V>(R(q == k ? 1 : 0)));
+#pragma unroll
+                        for (int m = 0; m < NB; ++m)
+                            msubc(e, widen(bcr<G>(Af[0][m], k)), widen(M[0][m]));
+                        const V ef = narrow<V>(e);
+#pragma unroll
+                        for (int i2 = 0; i2 < NB; ++i2) madd(upd[0][i2], bcr<G>(M[0][i2], k), ef);
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < NB; ++k) {
+                        W e[S];
+#pragma unroll
+                        for (int s = 0; s < S; ++s) e[s] = widen(mk<V>(R(s * G + q == k ? 1 : 0)));
+#pragma unroll
+                        for (int m = 0; m < NB; ++m) {
+                            const W amk = widen(bc<G>(Af[k / G][m], k % G));   // a_mk
+#pragma unroll
+                            for (int s = 0; s < S; ++s) msubc(e[s], amk, widen(M[s][m]));
+                        }
+#pragma unroll
+                        for (int s = 0; s < S; ++s) {
+                            const V ef = narrow<V>(e[s]);
+#pragma unroll
+                            for (int i2 = 0; i2 < NB; ++i2)
+                                madd(upd[s][i2], bc<G>(M[k / G][i2], k % G), ef);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int s = 0; s < S; ++s)
+#pragma unroll
+                    for (int i = 0; i < NB; ++i) {
+                        const int j = s * G + q;
+                        M[s][i] = (i == j) ? realpart_only(upd[s][i]) : upd[s][i];
+                    }
+            }
+        }
+
+        // ---- store: column j upper part (i <= j), lower part mirrored from the
+        // upper part of the later columns (exactly conjugate)
+        if (valid) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int j = s * G + q;
+                if (j < n) {
+#pragma unroll
+                    for (int i = 0; i < NB; ++i) {
+                        if (i < n && i <= j) {
+                            const V v = fail ? nan_value<V>() : M[s][i];
+                            x[i * ldx + j] = v;
+                            if (fill && i < j) x[j * ldx + i] = cj(v);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (valid && q == 0 && info_b) *info_b = (fail > n) ? 0 : fail;
+}
+
+// ---- uniform-batch kernel ---------------------------------------------------------
+constexpr int GROUP_BLOCK = 256;
+
+template <class V, int NB, int G, int OP, int METHOD, int MIXED>
+__global__ void __launch_bounds__(GROUP_BLOCK)
+k_group(const V* __restrict__ a, V* x, int64_t batch, int n, int64_t lda, int64_t sa,
+        int64_t ldx, int64_t sx, int ns_steps, int fill, int32_t* __restrict__ info,
+        typename vt<V>::real* __restrict__ dout)
+{
+    constexpr int MPB = GROUP_BLOCK / G;
+    const int q = threadIdx.x % G;
+    const int64_t b = (int64_t)blockIdx.x * MPB + threadIdx.x / G;
+    const bool valid = b < batch;
+    const int64_t bb = valid ? b : 0;
+    group_matrix<V, NB, G, OP, METHOD, MIXED>(a + bb * sa, lda, n, x + bb * sx, ldx, valid, fill,
+                                              ns_steps, q, info ? info + bb : nullptr,
+                                              dout ? dout + bb * n : nullptr);
+}
+
+template <class V, int NB, int G, int OP, int METHOD, int MIXED>
+static hipError_t group_run(const BatchArgs& p, int n, hipStream_t s)
+{
+    using Rt = typename vt<V>::real;
+    constexpr int MPB = GROUP_BLOCK / G;
+    const int64_t blocks = (p.batch + MPB - 1) / MPB;
+    hipLaunchKernelGGL((k_group<V, NB, G, OP, METHOD, MIXED>), dim3((unsigned)blocks),
+                       dim3(GROUP_BLOCK), 0, s, (const V*)p.a, (V*)p.x, p.batch, n, p.lda, p.sa,
+                       p.ldx, p.sx, p.ns_steps, p.fill, p.info, (Rt*)p.dout);
+    return hipGetLastError();
+}
+
+template <class V, int NB, int G>
+static hipError_t group_run_ops(int n, int op, int method, int mixed, const BatchArgs& p,
+                                hipStream_t s)
+{
+    constexpr bool f32 = sizeof(typename vt<V>::real) == 4;
+    if (op == OP_INV) {
+        if (mixed) {
+            if constexpr (f32) {
+                if (method == 0) return group_run<V, NB, G, OP_INV, 0, 1>(p, n, s);
+                return group_run<V, NB, G, OP_INV, 1, 1>(p, n, s);
+            }
+            return hipErrorNotSupported;
+        }
+        if (method == 0) return group_run<V, NB, G, OP_INV, 0, 0>(p, n, s);
+        return group_run<V, NB, G, OP_INV, 1, 0>(p, n, s);
+    }
+    if (op == OP_CHOL_FACTOR) return group_run<V, NB, G, OP_CHOL_FACTOR, 0, 0>(p, n, s);
+    if (op == OP_LDL_FACTOR) return group_run<V, NB, G, OP_LDL_FACTOR, 1, 0>(p, n, s);
+    return hipErrorNotSupported;
+}
+
+}  // namespace ci

@@ -63,3 +63,19 @@ hipError_t launch_tpm(int dtype, int n, int op, int method, int mixed, const Bat
 }
 
 }  // namespace ci
+
+namespace ci {
+
+hipError_t launch_group(int dtype, int n, int op, int method, int mixed, const BatchArgs& p,
+                        hipStream_t s)
+{
+    switch (dtype) {
+    case DT_F32: return launch_group_f32(n, op, method, mixed, p, s);
+    case DT_F64: return launch_group_f64(n, op, method, mixed, p, s);
+    case DT_C64: return launch_group_c64(n, op, method, mixed, p, s);
+    case DT_C128: return launch_group_c128(n, op, method, mixed, p, s);
+    default: return hipErrorNotSupported;
+    }
+}
+
+}  // namespace ci

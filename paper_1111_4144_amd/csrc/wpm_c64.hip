@@ -1,0 +1,13 @@
+// wpm_c64.hip -- LDS-resident group kernels (orders 17..32) for cf elements.
+#include "wpm_impl.hpp"
+
+namespace ci {
+
+hipError_t launch_wpm_c64(int n, int op, int method, int mixed, const BatchArgs& p,
+                            hipStream_t s)
+{
+    if (n <= 32) return wpm_run_ops<cf, 32>(n, op, method, mixed, p, s);
+    return hipErrorNotSupported;
+}
+
+}  // namespace ci

@@ -1,0 +1,14 @@
+// wpm_f32.hip -- LDS-resident group kernels (orders 17..64) for float elements.
+#include "wpm_impl.hpp"
+
+namespace ci {
+
+hipError_t launch_wpm_f32(int n, int op, int method, int mixed, const BatchArgs& p,
+                            hipStream_t s)
+{
+    if (n <= 32) return wpm_run_ops<float, 32>(n, op, method, mixed, p, s);
+    if (n <= 64) return wpm_run_ops<float, 64>(n, op, method, mixed, p, s);
+    return hipErrorNotSupported;
+}
+
+}  // namespace ci

@@ -51,21 +51,64 @@ def test_c64_small(n, method, prec, ns):
     print("n=%d %s %s ns=%d: max rel err %.3e, max err/kappa %.3e" % (n, method, prec, ns, e, r))
 
 
-@pytest.mark.parametrize("n", [1, 4, 7, 8, 11, 12, 16])
+@pytest.mark.parametrize("n", [1, 4, 7, 8, 11, 12, 16, 17, 24, 31, 32, 33, 48, 63, 64])
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 @pytest.mark.parametrize("method", ["chol", "ldl"])
 def test_real_small(n, dtype, method):
+    """Real SPD orders 1..64: thread-per-matrix, lane-group (<= 16) and LDS-resident
+    (17..64) kernels; 130 matrices = 2 full blocks + a ragged tail."""
     t = torch_cuda()
     rng = np.random.default_rng(100 + n)
     npd = np.float32 if dtype == "f32" else np.float64
     a = G.random_hpd(rng, 130, n, shift=0.5, complex_=False, dtype=npd)
-    precs = [("plain", 0)] + ([("mixed", 1)] if dtype == "f32" else [])
+    precs = [("plain", 0)] + ([("mixed", 1), ("mixed", 2)] if dtype == "f32" else [])
     xo, io = O.inv_prop(a, method)
     for prec, ns in precs:
         x, info = _inv(t, a, method=method, precision=prec, ns_steps=ns)
         assert np.array_equal(info, io)
         tol = TOL_FP64 if dtype == "f64" else TOL_FP32
-        assert_within(x, xo, a, tol, "%s n=%d %s %s" % (dtype, n, method, prec))
+        e, r = assert_within(x, xo, a, tol, "%s n=%d %s %s ns=%d" % (dtype, n, method, prec, ns))
+        print("%s n=%d %s %s ns=%d: max rel err %.3e, max err/kappa %.3e" % (dtype, n, method, prec, ns, e, r))
+
+
+@pytest.mark.parametrize("n", [9, 12, 16, 17, 24, 32])
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("method", ["chol", "ldl"])
+def test_complex_group(n, dtype, method):
+    """Complex orders beyond the thread-per-matrix range (lane groups / LDS)."""
+    t = torch_cuda()
+    npd = np.complex64 if dtype == "c64" else np.complex128
+    a = G.mimo(n, 300, seed=11 + n).astype(npd)
+    precs = [("plain", 0)] + ([("mixed", 1)] if dtype == "c64" else [])
+    xo, io = O.inv_prop(a, method)
+    for prec, ns in precs:
+        x, info = _inv(t, a, method=method, precision=prec, ns_steps=ns)
+        assert np.array_equal(info, io)
+        tol = TOL_FP64 if dtype == "c128" else TOL_FP32
+        e, r = assert_within(x, xo, a, tol, "%s n=%d %s %s ns=%d" % (dtype, n, method, prec, ns))
+        print("%s n=%d %s %s ns=%d: max rel err %.3e, max err/kappa %.3e" % (dtype, n, method, prec, ns, e, r))
+
+
+def test_group_failures_and_lower_nan():
+    """info / NaN fill and ignored lower triangle on the group and LDS kernels."""
+    t = torch_cuda()
+    for n in (16, 40):
+        a = G.random_hpd(np.random.default_rng(n), 70, n, shift=1.0, complex_=False)
+        a[5] = np.eye(n)
+        a[5, 3, 3] = -2.0
+        a[60, 1, n - 1] = np.nan
+        p = a.copy()
+        il = np.tril_indices(n, -1)
+        p[:, il[0], il[1]] = np.nan
+        for prec, ns, dt in [("plain", 0, np.float64), ("mixed", 1, np.float32)]:
+            x, info = _inv(t, p.astype(dt), precision=prec, ns_steps=ns)
+            xo, io = O.inv_prop(a.astype(dt))
+            assert np.array_equal(info, io) and info[5] == 4 and info[60] == n
+            assert np.all(np.isnan(x[5])) and np.all(np.isnan(x[60]))
+            good = np.ones(70, bool)
+            good[[5, 60]] = False
+            assert_within(x[good], xo[good], a[good].astype(dt),
+                          TOL_FP64 if dt == np.float64 else TOL_FP32, "group failures n=%d" % n)
 
 
 def test_nan_lower_triangle_is_ignored_and_deterministic():
