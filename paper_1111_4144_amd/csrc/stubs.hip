@@ -28,7 +28,5 @@ size_t varlen_workspace(int64_t) { return 0; }
 hipError_t launch_varlen(int, int64_t, const int32_t*, const int64_t*, int, const void*, void*,
                          int, int, int, int, int32_t*, void*, hipStream_t)
 { return hipErrorNotSupported; }
-hipError_t launch_backward(int, int, const void*, const void*, void*, int64_t, int64_t, hipStream_t)
-{ return hipErrorNotSupported; }
 
 }  // namespace ci

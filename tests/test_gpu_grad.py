@@ -1,0 +1,113 @@
+"""GPU parity of the hand-written backward gA = -X Gh X (chol_inverse_backward)
+and of the CholInverse autograd.Function.
+
+Checks: the kernel on the oracle's own X against the oracle's analytic
+gradient; the full FP32 forward + backward chain against the oracle; central
+finite differences (h = 1e-6) of the FP64 GPU forward along Hermitian
+directions against the FP64 GPU backward.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1111_4144_amd import inputs as G
+from tests.helpers import TOL_FP32, kappas, rel_err, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu(t, a):
+    return t.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("n", [1, 3, 4, 7, 8, 12, 16, 20, 32, 40, 64])
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128, np.float32, np.float64])
+def test_backward_kernel_matches_oracle_grad(n, dtype):
+    t = torch_cuda()
+    from paper_1111_4144_amd import api
+    if n > 32 and dtype == np.complex128:
+        pytest.skip("complex128 backward is built up to order 32")
+    cplx = np.issubdtype(dtype, np.complexfloating)
+    rng = np.random.default_rng(7 + n)
+    a = G.random_hpd(rng, 97, n, shift=1.0, complex_=cplx)
+    xo, _ = O.inv_prop(a)
+    g = rng.standard_normal((97, n, n)) + (1j * rng.standard_normal((97, n, n)) if cplx else 0)
+    xs, gs = xo.astype(dtype), g.astype(dtype)
+    ga = api.inverse_backward(_gpu(t, xs), _gpu(t, gs)).cpu().numpy()
+    want = O.grad(xs, gs)                    # oracle on the same (rounded) inputs
+    err = rel_err(ga, want)
+    tol = 1e-5 if dtype in (np.complex64, np.float32) else 1e-12
+    assert err.max() <= tol, err.max()
+    assert np.array_equal(ga, np.conj(np.swapaxes(ga, -1, -2)))   # exactly Hermitian
+
+
+def test_forward_backward_chain_16x16_c64():
+    """The differentiation workload's shape: 16x16 complex64, A = B B^H + I, G iid
+    CN(0, 1); mixed-precision forward + backward vs the oracle's analytic
+    gradient at the exact inverse."""
+    t = torch_cuda()
+    from paper_1111_4144_amd import api
+    a, g = G.grad_16(count=2000)
+    ag = _gpu(t, a).requires_grad_(True)
+    x = api.CholInverse.apply(ag, "chol", "mixed", 1)
+    x.backward(_gpu(t, g))
+    ga = ag.grad.cpu().numpy()
+    xo, _ = O.inv_prop(a)
+    want = O.grad(xo, g)
+    err = rel_err(ga, want)
+    k = kappas(a)
+    bound = 2 * TOL_FP32 * k + 1e-5
+    assert np.all(err <= bound), (err / bound).max()
+    print("grad max rel err %.3e (bound min %.3e)" % (err.max(), bound.min()))
+
+
+def test_finite_differences_fp64():
+    t = torch_cuda()
+    from paper_1111_4144_amd import api
+    rng = np.random.default_rng(3)
+    n = 16
+    a = G.random_hpd(rng, 1, n, shift=1.0)[0]
+    g = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+
+    def loss(m):
+        x = api.inverse(_gpu(t, m[None]))[0].cpu().numpy()
+        return float(np.real(np.sum(np.conj(g) * x)))
+
+    x = api.inverse(_gpu(t, a[None]))
+    ga = api.inverse_backward(x, _gpu(t, g[None]))[0].cpu().numpy()
+    h = 1e-6
+    dirs = []
+    for (i, j) in [(0, 0), (3, 3), (0, 5), (7, 2), (15, 14)]:
+        e = np.zeros((n, n), np.complex128)
+        if i == j:
+            e[i, i] = 1
+        else:
+            e[i, j] = e[j, i] = 1 / np.sqrt(2)
+        dirs.append(e)
+        if i != j:
+            e2 = np.zeros((n, n), np.complex128)
+            e2[i, j], e2[j, i] = 1j / np.sqrt(2), -1j / np.sqrt(2)
+            dirs.append(e2)
+    z = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    dirs.append((z + np.conj(z.T)) / np.linalg.norm(z + np.conj(z.T)))
+    for e in dirs:
+        fd = (loss(a + h * e) - loss(a - h * e)) / (2 * h)
+        an = float(np.real(np.sum(np.conj(ga) * e)))
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (fd, an)
+
+
+def test_autograd_matches_torch_reference_on_hermitian_directions():
+    """Against torch.linalg.inv's own autograd (CPU, complex128): equal after the
+    Hermitian projection (the method's domain is Hermitian A)."""
+    t = torch_cuda()
+    from paper_1111_4144_amd import api
+    rng = np.random.default_rng(5)
+    a = G.random_hpd(rng, 4, 6, shift=1.0)
+    g = rng.standard_normal((4, 6, 6)) + 1j * rng.standard_normal((4, 6, 6))
+    ac = t.tensor(a, dtype=t.complex128, requires_grad=True)
+    t.linalg.inv(ac).backward(t.tensor(g))
+    ref = ac.grad.numpy()
+    ref = 0.5 * (ref + np.conj(np.swapaxes(ref, -1, -2)))
+    ag = _gpu(t, a).requires_grad_(True)
+    api.CholInverse.apply(ag).backward(_gpu(t, g))
+    assert np.abs(ag.grad.cpu().numpy() - ref).max() <= 1e-11 * np.abs(ref).max()
