@@ -1,0 +1,265 @@
+"""Benchmark of the batched Hermitian positive-definite inversion on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
+
+Workload (one step): the MIMO-shaped batch -- 1,048,576 complex64 Hermitian
+positive-definite matrices, half of order 8 and half of order 16,
+A = B B^H + sigma I with sigma = 10^U(-2, 0) -- inverted by the Section IV
+method in mixed precision (FP32 bulk, FP64 pivots, one Newton-Schulz step
+with an FP64 residual).  Inputs are resident in HBM before timing; the step
+is the two batched launches (one per order).  `value` = inverses per second
+over the whole batch.
+
+The printed JSON line also carries
+  roofline      for the kernel that dominates the step (per-launch duration
+                from HIP events on its stream; algorithmic bytes per launch)
+  cpu_baseline  the FP64 CPU oracle, single-threaded, on a bounded sample
+  details       per-order rates, the plain-FP64 path on the same matrices, the
+                measured errors against the oracle, the differentiation
+                workload (forward + backward), and the other workloads.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12            # bytes/s, MI355X published HBM3E bandwidth
+COUNT_PER_ORDER = 524288     # each half of the MIMO batch
+
+
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def _time_loop(torch, fns, steps, warmup):
+    """Run `fns` (list of callables, each one kernel launch) per step; return the
+    mean step time (ms) and the mean per-launch duration of each fn (ms), all
+    measured with HIP events on the current stream."""
+    for _ in range(warmup):
+        for f in fns:
+            f()
+    torch.cuda.synchronize()
+    per = [[_events(torch) for _ in range(steps)] for _ in fns]
+    t0, t1 = _events(torch)
+    t0.record()
+    for s in range(steps):
+        for i, f in enumerate(fns):
+            per[i][s][0].record()
+            f()
+            per[i][s][1].record()
+    t1.record()
+    torch.cuda.synchronize()
+    step_ms = t0.elapsed_time(t1) / steps
+    launch_ms = [float(np.mean([a.elapsed_time(b) for a, b in per[i]])) for i in range(len(fns))]
+    return step_ms, launch_ms
+
+
+def _errors(x, a, oracle, idx):
+    """max relative Frobenius error and max err/kappa over sampled matrices."""
+    xo, _ = oracle.inv_prop(a[idx])
+    xs = x[idx].astype(np.complex128)
+    num = np.sqrt(np.sum(np.abs(xs - xo) ** 2, axis=(-1, -2)))
+    den = np.sqrt(np.sum(np.abs(xo) ** 2, axis=(-1, -2)))
+    err = num / den
+    kap = np.array([oracle.kappa2(m.astype(np.complex128)) for m in a[idx]])
+    return float(err.max()), float((err / kap).max())
+
+
+def _traffic(kernel_key, launches_bytes):
+    """HBM traffic per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            tab = json.load(f)
+        from paper_1111_4144_amd import build as B
+        ent = tab.get(kernel_key)
+        if not ent or ent.get("source_digest") != B.source_digest():
+            return None
+        return float(ent["fetch_bytes"] + ent["write_bytes"])
+    except (OSError, ValueError, KeyError):
+        return None
+
+
+def cpu_baseline(target_seconds=10.0):
+    """The oracle (plain C, FP64, one thread) on the leading 65,536 matrices of each
+    half of the MIMO batch, repeated until about target_seconds of CPU work;
+    matrices/s."""
+    import oracle as O
+    from paper_1111_4144_amd import inputs as G
+    n_each = 65536
+    a8 = G.mimo(8, n_each)
+    a16 = G.mimo(16, n_each)
+    done = 0
+    t = time.perf_counter()
+    while True:
+        O.inv_prop(a8)
+        O.inv_prop(a16)
+        done += 2 * n_each
+        secs = time.perf_counter() - t
+        if secs >= target_seconds:
+            break
+    return {"value": done / secs, "unit": "inverses/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d 8x8 + %d 16x16 matrices of the MIMO batch, inverted %d times "
+                      "in complex128 by the single-threaded oracle (%.1f s)"
+                      % (n_each, n_each, done // (2 * n_each), secs)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-extras", action="store_true", help="skip the secondary workloads")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 1 GiB three times (the reference "
+                         "kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs on a single MI355X and "
+              "has no multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": src.numel() * 4, "launches": 3}))
+        return
+
+    import oracle as O
+    from paper_1111_4144_amd import api, inputs as G
+
+    t_gen = time.perf_counter()
+    a8 = G.mimo(8, COUNT_PER_ORDER)
+    a16 = G.mimo(16, COUNT_PER_ORDER)
+    gen_s = time.perf_counter() - t_gen
+    A8 = torch.from_numpy(a8).to(dev)
+    A16 = torch.from_numpy(a16).to(dev)
+    X8 = torch.empty_like(A8)
+    X16 = torch.empty_like(A16)
+    torch.cuda.synchronize()
+
+    def f8():
+        api.inverse(A8, precision="mixed", ns_steps=1, out=X8)
+
+    def f16():
+        api.inverse(A16, precision="mixed", ns_steps=1, out=X16)
+
+    step_ms, (ms8, ms16) = _time_loop(torch, [f8, f16], args.steps, args.warmup)
+    total = 2 * COUNT_PER_ORDER
+    value = total / (step_ms / 1e3)
+
+    # roofline of the dominant kernel (algorithmic bytes: A in + X out, dense)
+    dom = "16x16" if ms16 >= ms8 else "8x8"
+    dom_ms = max(ms8, ms16)
+    n_dom = 16 if dom == "16x16" else 8
+    bytes_launch = COUNT_PER_ORDER * n_dom * n_dom * 8 * 2
+    achieved = bytes_launch / (dom_ms / 1e3)
+    kernel_key = "mimo_c64_%s_mixed_ns1" % dom
+    roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK,
+                "traffic": _traffic(kernel_key, bytes_launch),
+                "kernel": kernel_key, "launch_ms": dom_ms,
+                "bytes_per_launch": bytes_launch}
+
+    details = {
+        "rate_8x8_inv_per_s": COUNT_PER_ORDER / (ms8 / 1e3),
+        "rate_16x16_inv_per_s": COUNT_PER_ORDER / (ms16 / 1e3),
+        "hbm_frac_8x8": COUNT_PER_ORDER * 1024 / (ms8 / 1e3) / HBM_PEAK,
+        "hbm_frac_16x16": COUNT_PER_ORDER * 4096 / (ms16 / 1e3) / HBM_PEAK,
+        "launch_ms_8x8": ms8, "launch_ms_16x16": ms16,
+        "input_generation_s": gen_s,
+    }
+
+    # accuracy of the timed outputs against the oracle (sampled matrices)
+    rng = np.random.default_rng(0)
+    idx8 = rng.choice(COUNT_PER_ORDER, 1024, replace=False)
+    idx16 = rng.choice(COUNT_PER_ORDER, 1024, replace=False)
+    x8 = X8.cpu().numpy()
+    x16 = X16.cpu().numpy()
+    e8, r8 = _errors(x8, a8, O, idx8)
+    e16, r16 = _errors(x16, a16, O, idx16)
+    details["mixed_max_rel_err"] = max(e8, e16)
+    details["mixed_max_err_over_kappa"] = max(r8, r16)
+    del x8, x16
+
+    if not args.no_extras:
+        # plain FP64 on the same matrices (complex128), the speedup baseline
+        B8 = A8.to(torch.complex128)
+        B16 = A16.to(torch.complex128)
+        Y8 = torch.empty_like(B8)
+        Y16 = torch.empty_like(B16)
+        p_ms, (p8, p16) = _time_loop(
+            torch, [lambda: api.inverse(B8, out=Y8), lambda: api.inverse(B16, out=Y16)],
+            max(3, args.steps // 2), 2)
+        pe8, pr8 = _errors(Y8.cpu().numpy(), a8, O, idx8)
+        pe16, pr16 = _errors(Y16.cpu().numpy(), a16, O, idx16)
+        details["plain_fp64_inv_per_s"] = total / (p_ms / 1e3)
+        details["plain_fp64_max_rel_err"] = max(pe8, pe16)
+        details["speedup_mixed_vs_plain_fp64"] = p_ms / step_ms
+        del B8, B16, Y8, Y16
+        # mixed precision without refinement and plain FP32, for context
+        z_ms, _ = _time_loop(torch, [lambda: api.inverse(A8, precision="mixed", ns_steps=0, out=X8),
+                                     lambda: api.inverse(A16, precision="mixed", ns_steps=0, out=X16)],
+                             max(3, args.steps // 2), 2)
+        details["mixed_ns0_inv_per_s"] = total / (z_ms / 1e3)
+        # differentiation workload: 65,536 complex64 16x16, forward + backward
+        ag, gg = G.grad_16()
+        AG = torch.from_numpy(ag).to(dev)
+        GG = torch.from_numpy(gg).to(dev)
+        XG = torch.empty_like(AG)
+        state = {}
+
+        def fwd():
+            api.inverse(AG, precision="mixed", ns_steps=1, out=XG)
+
+        def bwd():
+            state["ga"] = api.inverse_backward(XG, GG)
+
+        g_ms, (gf, gb) = _time_loop(torch, [fwd, bwd], max(3, args.steps // 2), 2)
+        details["grad16_fwd_bwd_inv_per_s"] = ag.shape[0] / (g_ms / 1e3)
+        details["grad16_bwd_hbm_frac"] = ag.shape[0] * 6144 / (gb / 1e3) / HBM_PEAK
+        ga = state["ga"].cpu().numpy()
+        sub = np.arange(0, ag.shape[0], 64)
+        xo, _ = O.inv_prop(ag[sub])
+        want = O.grad(xo, gg[sub])
+        gerr = np.sqrt(np.sum(np.abs(ga[sub] - want) ** 2, axis=(-1, -2))) / \
+            np.sqrt(np.sum(np.abs(want) ** 2, axis=(-1, -2)))
+        details["grad16_max_rel_err"] = float(gerr.max())
+        del AG, GG, XG
+
+    line = {
+        "metric": "inverses/s (8x8 c64 batch), TFLOP/s N=8192, fwd+bwd vs plain @ stated err",
+        "value": value, "unit": "inverses/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": step_ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64 (FP32 + FP64 pivots/residual)",
+        "data": "synthetic (seeded A = B B^H + sigma I)",
+        "config": {"workload": "MIMO batch: 524,288 8x8 + 524,288 16x16 complex64 HPD, "
+                               "mixed precision, 1 Newton-Schulz step", "global_batch": total,
+                   "orders": [8, 16], "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": None if args.no_cpu else cpu_baseline(),
+        "details": details,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

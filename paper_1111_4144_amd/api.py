@@ -83,7 +83,7 @@ def inverse(A: torch.Tensor, *, method="chol", precision="plain", ns_steps=None,
         _check_device(out)
         if out.shape != A3.shape or not out.is_contiguous() or out.dtype != A.dtype:
             raise ValueError("out must be a contiguous tensor shaped like A")
-    info = torch.zeros(B, dtype=torch.int32, device=A.device)
+    info = torch.empty(B, dtype=torch.int32, device=A.device)   # every entry is written
     opts = L.make_opts(method, precision, ns_steps, fill_lower)
     dt = _dtype_code(A)
     lib = L.lib()
@@ -120,7 +120,7 @@ def inverse_varlen(packed: torch.Tensor, sizes: torch.Tensor, offsets: torch.Ten
     if n_max is None:
         n_max = int(sizes.max()) if B else 1
     X = out if out is not None else torch.empty_like(packed)
-    info = torch.zeros(B, dtype=torch.int32, device=packed.device)
+    info = torch.empty(B, dtype=torch.int32, device=packed.device)   # every entry is written
     opts = L.make_opts(method, precision, ns_steps, fill_lower)
     lib = L.lib()
     dt = _dtype_code(packed)

@@ -39,8 +39,16 @@ def _sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
 
 
-def _compile(src, verbose):
+def _newest_header():
+    hs = glob.glob(os.path.join(CSRC, "*.hpp")) + [os.path.join(INCLUDE, "cholinv.h")]
+    return max(os.path.getmtime(h) for h in hs)
+
+
+def _compile(src, verbose, incremental=False):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if incremental and os.path.exists(obj) and \
+            os.path.getmtime(obj) > max(os.path.getmtime(src), _newest_header()):
+        return obj
     cmd = [HIPCC, *CXXFLAGS, "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -54,12 +62,16 @@ def _compile(src, verbose):
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
+def build(jobs: int | None = None, verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source (incremental=True skips objects newer than their
+    inputs; the default always recompiles) and link the library."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = _sources()
     jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))
+    # the longest translation units first, so they do not finish last
+    srcs = sorted(srcs, key=lambda p: -os.path.getsize(p) if p.endswith(".hip") else 0)
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
+        objs = list(ex.map(lambda s: _compile(s, verbose, incremental), srcs))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
@@ -81,6 +93,7 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("-j", type=int, default=None)
     ap.add_argument("-v", action="store_true")
+    ap.add_argument("--incremental", action="store_true")
     a = ap.parse_args()
-    print(build(a.j, a.v))
+    print(build(a.j, a.v, a.incremental))
     sys.exit(0)

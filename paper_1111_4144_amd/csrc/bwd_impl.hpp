@@ -16,6 +16,7 @@
 #pragma once
 
 #include "group_impl.hpp"
+#include "tpm_impl.hpp"
 #include "wpm_impl.hpp"
 
 namespace ci {
@@ -51,34 +52,38 @@ k_bwd_group(const V* __restrict__ x, const V* __restrict__ g, V* __restrict__ ga
             Hc[s][k] = hv;
         }
     }
-    // T = Gh X
+    // T = Gh X: t_ij = sum_k Gh_ik x_kj, Gh_ik from the owner of column k
     V T[S][NB];
 #pragma unroll
-    for (int s = 0; s < S; ++s)
+    for (int i = 0; i < NB; ++i) {
 #pragma unroll
-        for (int i = 0; i < NB; ++i) T[s][i] = mk<V>(R(0));
+        for (int s = 0; s < S; ++s) T[s][i] = mk<V>(R(0));
 #pragma unroll
-    for (int k = 0; k < NB; ++k) {
+        for (int k = 0; k < NB; ++k) {
+            // the empty asm on the accumulator keeps each product next to its
+            // broadcast (otherwise every broadcast is hoisted and stays live)
+            const V hik = bc<G>(Hc[k / G][i], k % G);
 #pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            const V hik = bc<G>(Hc[k / G][i], k % G);     // Gh_ik
-#pragma unroll
-            for (int s = 0; s < S; ++s) madd(T[s][i], hik, Xc[s][k]);
+            for (int s = 0; s < S; ++s) {
+                madd(T[s][i], hik, Xc[s][k]);
+                opaque(T[s][i]);
+            }
         }
     }
-    // gA = -X T
+    // gA = -X T: ga_ij = -sum_k x_ik t_kj, x_ik from the owner of column k
     V O[S][NB];
 #pragma unroll
-    for (int s = 0; s < S; ++s)
+    for (int i = 0; i < NB; ++i) {
 #pragma unroll
-        for (int i = 0; i < NB; ++i) O[s][i] = mk<V>(R(0));
+        for (int s = 0; s < S; ++s) O[s][i] = mk<V>(R(0));
 #pragma unroll
-    for (int k = 0; k < NB; ++k) {
+        for (int k = 0; k < NB; ++k) {
+            const V xik = bc<G>(Xc[k / G][i], k % G);
 #pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            const V xik = bc<G>(Xc[k / G][i], k % G);     // x_ik
-#pragma unroll
-            for (int s = 0; s < S; ++s) msub(O[s][i], xik, T[s][k]);
+            for (int s = 0; s < S; ++s) {
+                msub(O[s][i], xik, T[s][k]);
+                opaque(O[s][i]);
+            }
         }
     }
     // upper half of column j and its conjugate mirror (exactly Hermitian)

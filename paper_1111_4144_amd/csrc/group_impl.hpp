@@ -26,6 +26,16 @@
 
 namespace ci {
 
+#ifndef CI_OPAQUE_DEFINED
+#define CI_OPAQUE_DEFINED
+// An empty asm that claims to modify a register value: the compiler must keep
+// the value in a VGPR and cannot move its producer past this point.
+CI_D void opaque(float& v) { asm volatile("" : "+v"(v)); }
+CI_D void opaque(double& v) { asm volatile("" : "+v"(v)); }
+CI_D void opaque(cf& v) { asm volatile("" : "+v"(v.re), "+v"(v.im)); }
+CI_D void opaque(cd& v) { asm volatile("" : "+v"(v.re), "+v"(v.im)); }
+#endif
+
 // ---- cross-lane broadcast inside a group of G lanes ---------------------------
 template <int G, int K>
 CI_D int bc32_k(int v)
@@ -192,9 +202,13 @@ CI_D void group_matrix(const V* __restrict__ a, int64_t lda, int n, V* x, int64_
             const V rik = bc<G>(M[k / G][i], k % G);
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-                if (s * G + G - 1 >= k) msubc(M[s][k], rik, wv[s]);
+                if (s * G + G - 1 >= k) {
+                    msubc(M[s][k], rik, wv[s]);
+                    opaque(M[s][k]);   // product next to its broadcast (bounds live ranges)
+                }
             }
         }
+        __builtin_amdgcn_sched_barrier(0);   // bound live ranges between steps
     }
 
     if constexpr (OP == OP_CHOL_FACTOR || OP == OP_LDL_FACTOR) {
@@ -228,7 +242,10 @@ CI_D void group_matrix(const V* __restrict__ a, int64_t lda, int n, V* x, int64_
             for (int k = i + 1; k < NB; ++k) {
                 const V rik = bc<G>(M[k / G][i], k % G);
 #pragma unroll
-                for (int s = 0; s < S; ++s) msub(acc[s], rik, M[s][k]);
+                for (int s = 0; s < S; ++s) {
+                    msub(acc[s], rik, M[s][k]);
+                    opaque(acc[s]);
+                }
             }
             V xnew[S];
 #pragma unroll
@@ -246,6 +263,7 @@ CI_D void group_matrix(const V* __restrict__ a, int64_t lda, int n, V* x, int64_
             for (int k = i + 1; k < NB; ++k) {
                 const V rik = bc<G>(M[k / G][i], k % G);
                 msub(d, rik, M[si][k]);
+                opaque(d);
             }
             d = realpart_only((METHOD == 0) ? scal(d, sall[i]) : d);
             // row i of X replaces row i of R
@@ -254,6 +272,7 @@ CI_D void group_matrix(const V* __restrict__ a, int64_t lda, int n, V* x, int64_
                 const int j = s * G + q;
                 M[s][i] = (j > i) ? xnew[s] : ((j == i) ? d : M[s][i]);
             }
+            __builtin_amdgcn_sched_barrier(0);
         }
 
         // ---- Newton-Schulz: X <- X + X(I - A X), residual in FP64 -------------
@@ -267,7 +286,7 @@ CI_D void group_matrix(const V* __restrict__ a, int64_t lda, int n, V* x, int64_
                 for (int s = 0; s < S; ++s)
 #pragma unroll
                     for (int i = 0; i < NB; ++i) upd[s][i] = M[s][i];
-                if constexpr (S == 1) {
+                if constexpr (S == 1 && NB > 16) {
                     // one column per lane: the source lane of column k is k itself,
                     // so k can stay a run-time loop (code size NB^2, not NB^3)
 #pragma unroll 1
@@ -290,15 +309,21 @@ CI_D void group_matrix(const V* __restrict__ a, int64_t lda, int n, V* x, int64_
                         for (int m = 0; m < NB; ++m) {
                             const W amk = widen(bc<G>(Af[k / G][m], k % G));   // a_mk
 #pragma unroll
-                            for (int s = 0; s < S; ++s) msubc(e[s], amk, widen(M[s][m]));
+                            for (int s = 0; s < S; ++s) {
+                                msubc(e[s], amk, widen(M[s][m]));
+                                opaque(e[s]);
+                            }
                         }
 #pragma unroll
                         for (int s = 0; s < S; ++s) {
                             const V ef = narrow<V>(e[s]);
 #pragma unroll
-                            for (int i2 = 0; i2 < NB; ++i2)
+                            for (int i2 = 0; i2 < NB; ++i2) {
                                 madd(upd[s][i2], bc<G>(M[k / G][i2], k % G), ef);
+                                opaque(upd[s][i2]);
+                            }
                         }
+                        __builtin_amdgcn_sched_barrier(0);
                     }
                 }
 #pragma unroll

@@ -24,9 +24,5 @@ hipError_t large_factor(int, int64_t, void*, int64_t, int32_t*, void*, hipStream
 hipError_t large_inverse(int, int64_t, const void*, int64_t, void*, int64_t, int, int, int,
                          int32_t*, void*, hipStream_t)
 { return hipErrorNotSupported; }
-size_t varlen_workspace(int64_t) { return 0; }
-hipError_t launch_varlen(int, int64_t, const int32_t*, const int64_t*, int, const void*, void*,
-                         int, int, int, int, int32_t*, void*, hipStream_t)
-{ return hipErrorNotSupported; }
 
 }  // namespace ci

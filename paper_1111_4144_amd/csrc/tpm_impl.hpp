@@ -52,10 +52,13 @@ CI_D typename vt<V>::real abs2_r(V a) {
 // An empty asm that claims to modify a register value: the compiler must keep
 // the value in a VGPR and cannot reuse anything it derived from it before.
 // Used so that FP64 copies of A are rebuilt per column instead of all kept live.
+#ifndef CI_OPAQUE_DEFINED
+#define CI_OPAQUE_DEFINED
 CI_D void opaque(float& v) { asm volatile("" : "+v"(v)); }
 CI_D void opaque(double& v) { asm volatile("" : "+v"(v)); }
 CI_D void opaque(cf& v) { asm volatile("" : "+v"(v.re), "+v"(v.im)); }
 CI_D void opaque(cd& v) { asm volatile("" : "+v"(v.re), "+v"(v.im)); }
+#endif
 
 // ---- wide memory moves ------------------------------------------------------
 template <class V> constexpr int WORDS = sizeof(V) / 4;
@@ -785,12 +788,13 @@ static hipError_t tpm_run_n(int op, int method, int mixed, const BatchArgs& p, h
     return hipErrorNotSupported;
 }
 
-template <class V, int... Ns>
-static hipError_t tpm_run_dtype(int n, int op, int method, int mixed, const BatchArgs& p,
+// Orders LO+0 .. LO+len-1.
+template <class V, int LO, int... Ns>
+static hipError_t tpm_run_range(int n, int op, int method, int mixed, const BatchArgs& p,
                                 hipStream_t s, std::integer_sequence<int, Ns...>)
 {
     hipError_t r = hipErrorNotSupported;
-    ((n == Ns + 1 ? (r = tpm_run_n<V, Ns + 1>(op, method, mixed, p, s), 0) : 0), ...);
+    ((n == LO + Ns ? (r = tpm_run_n<V, LO + Ns>(op, method, mixed, p, s), 0) : 0), ...);
     return r;
 }
 

@@ -1,0 +1,221 @@
+// varlen_impl.hpp -- one persistent launch for a packed batch of matrices of
+// uneven orders (1..64).  Included by one translation unit per element type.
+//
+// Device-side prologue (no host synchronisation, capturable in a HIP graph):
+//   1. count   histogram of the orders;
+//   2. scan    orders are laid out largest first: per order n its first item
+//              in the sorted index list and its tile range;
+//   3. scatter every matrix index into the sorted list.
+// Tiles: an order n <= 8 tile is up to 64 matrices (one lane each, registers);
+// 9..16 up to 4 matrices (16-lane groups padded to 16 with the identity,
+// which leaves the n x n block exact); 17..32 up to 2 and 33..64 one matrix
+// (LDS-resident, one lane per column).  The persistent kernel's waves take
+// tiles from an atomic counter until none are left (every wave reaches that
+// exit), so the largest, slowest tiles start first and the small ones fill in.
+// Results do not depend on which wave takes which tile.
+#pragma once
+
+#include "group_impl.hpp"
+#include "tpm_impl.hpp"
+#include "wpm_impl.hpp"
+
+namespace ci {
+
+struct VarlenPlan {
+    int next;              // tile counter of the persistent kernel
+    int ntiles;
+    int count[65];         // matrices per order
+    int item_start[65];    // first position of order n in the sorted list
+    int tile_start[65];    // tile range of order n: [tile_start, tile_end)
+    int tile_end[65];
+    int cursor[65];        // scatter cursors
+};
+
+CI_D int vl_tile_size(int n) { return n <= 8 ? 64 : n <= 16 ? 4 : n <= 32 ? 2 : 1; }
+
+__global__ void k_vl_init(VarlenPlan* plan)
+{
+    int* p = reinterpret_cast<int*>(plan);
+    for (int i = threadIdx.x; i < (int)(sizeof(VarlenPlan) / sizeof(int)); i += blockDim.x) p[i] = 0;
+}
+
+__global__ void k_vl_count(const int32_t* __restrict__ ns, int64_t batch, int nmax,
+                           VarlenPlan* plan, int32_t* __restrict__ info)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    const int n = ns[b];
+    if (n < 0 || n > nmax) {
+        if (info) info[b] = -1;
+    } else if (n == 0) {
+        if (info) info[b] = 0;
+    } else {
+        atomicAdd(&plan->count[n], 1);
+    }
+}
+
+__global__ void k_vl_scan(VarlenPlan* plan)
+{
+    if (threadIdx.x != 0) return;
+    int items = 0, tiles = 0;
+    for (int n = 64; n >= 1; --n) {
+        const int c = plan->count[n];
+        const int ts = vl_tile_size(n);
+        plan->item_start[n] = items;
+        plan->tile_start[n] = tiles;
+        tiles += (c + ts - 1) / ts;
+        plan->tile_end[n] = tiles;
+        items += c;
+    }
+    plan->ntiles = tiles;
+    plan->next = 0;
+}
+
+__global__ void k_vl_scatter(const int32_t* __restrict__ ns, int64_t batch, int nmax,
+                             VarlenPlan* plan, int32_t* __restrict__ sorted)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    const int n = ns[b];
+    if (n < 1 || n > nmax) return;
+    const int pos = plan->item_start[n] + atomicAdd(&plan->cursor[n], 1);
+    sorted[pos] = (int32_t)b;
+}
+
+// One lane, one matrix of order N (dense, leading dimension N).
+template <class V, int N, int METHOD, int MIXED>
+CI_D int vl_lane(const V* __restrict__ a, V* x, int ns_steps, int fill)
+{
+    V A[N][N];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = i; j < N; ++j) A[i][j] = a[i * N + j];
+    return tpm_body<V, N, OP_INV, METHOD, MIXED>(A, OutDense<V>{x, N, fill != 0}, ns_steps, false,
+                                                 nullptr, nullptr);
+}
+
+template <class V, int METHOD, int MIXED>
+__global__ void __launch_bounds__(64)
+k_varlen(const V* __restrict__ a, V* x, const int64_t* __restrict__ offs,
+         const int32_t* __restrict__ sorted, VarlenPlan* plan, int ns_steps, int fill,
+         int32_t* __restrict__ info)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int s_tile;
+    const int lane = threadIdx.x;
+    for (;;) {
+        if (lane == 0) s_tile = atomicAdd(&plan->next, 1);
+        __syncthreads();
+        const int t = s_tile;
+        __syncthreads();
+        if (t >= plan->ntiles) break;
+        int n = 64;
+        while (n > 1 && t >= plan->tile_end[n]) --n;
+        const int per = vl_tile_size(n);
+        const int k = t - plan->tile_start[n];
+        const int first = plan->item_start[n] + k * per;
+        const int cnt = min(per, plan->count[n] - k * per);
+        if (n <= 8) {
+            if (lane < cnt) {
+                const int b = sorted[first + lane];
+                const int64_t o = offs[b];
+                int f = 0;
+                switch (n) {
+                case 1: f = vl_lane<V, 1, METHOD, MIXED>(a + o, x + o, ns_steps, fill); break;
+                case 2: f = vl_lane<V, 2, METHOD, MIXED>(a + o, x + o, ns_steps, fill); break;
+                case 3: f = vl_lane<V, 3, METHOD, MIXED>(a + o, x + o, ns_steps, fill); break;
+                case 4: f = vl_lane<V, 4, METHOD, MIXED>(a + o, x + o, ns_steps, fill); break;
+                case 5: f = vl_lane<V, 5, METHOD, MIXED>(a + o, x + o, ns_steps, fill); break;
+                case 6: f = vl_lane<V, 6, METHOD, MIXED>(a + o, x + o, ns_steps, fill); break;
+                case 7: f = vl_lane<V, 7, METHOD, MIXED>(a + o, x + o, ns_steps, fill); break;
+                default: f = vl_lane<V, 8, METHOD, MIXED>(a + o, x + o, ns_steps, fill); break;
+                }
+                if (info) info[b] = f;
+            }
+        } else if (n <= 16) {
+            const int g = lane / 16;
+            const bool valid = g < cnt;
+            const int b = sorted[first + (valid ? g : 0)];
+            const int64_t o = offs[b];
+            group_matrix<V, 16, 16, OP_INV, METHOD, MIXED>(a + o, n, n, x + o, n, valid, fill,
+                                                           ns_steps, lane % 16,
+                                                           (valid && info) ? info + b : nullptr,
+                                                           nullptr);
+        } else if (n <= 32) {
+            const int g = lane / 32;
+            const bool valid = g < cnt;
+            const int b = sorted[first + (valid ? g : 0)];
+            const int64_t o = offs[b];
+            wpm_matrix<V, 32, OP_INV, METHOD, MIXED>(
+                a + o, x + o, n, valid, n, n, ns_steps, fill, (valid && info) ? info + b : nullptr,
+                nullptr, smem_raw + (size_t)g * wpm_smem_per_matrix<V, 32, MIXED>(), lane % 32);
+        } else {
+            const int b = sorted[first];
+            const int64_t o = offs[b];
+            wpm_matrix<V, 64, OP_INV, METHOD, MIXED>(a + o, x + o, n, true, n, n, ns_steps, fill,
+                                                     info ? info + b : nullptr, nullptr, smem_raw,
+                                                     lane);
+        }
+        __syncthreads();
+    }
+}
+
+constexpr size_t varlen_plan_bytes() { return (sizeof(VarlenPlan) + 255) / 256 * 256; }
+
+template <class V, int METHOD, int MIXED>
+static hipError_t varlen_run(int64_t batch, const int32_t* n_dev, const int64_t* off_dev, int n_max,
+                             const void* a, void* x, int ns_steps, int fill, int32_t* info,
+                             void* work, hipStream_t s)
+{
+    VarlenPlan* plan = reinterpret_cast<VarlenPlan*>(work);
+    int32_t* sorted = reinterpret_cast<int32_t*>((char*)work + varlen_plan_bytes());
+    const unsigned gb = (unsigned)((batch + 255) / 256);
+    hipLaunchKernelGGL(k_vl_init, dim3(1), dim3(256), 0, s, plan);
+    hipLaunchKernelGGL(k_vl_count, dim3(gb), dim3(256), 0, s, n_dev, batch, n_max, plan, info);
+    hipLaunchKernelGGL(k_vl_scan, dim3(1), dim3(64), 0, s, plan);
+    hipLaunchKernelGGL(k_vl_scatter, dim3(gb), dim3(256), 0, s, n_dev, batch, n_max, plan, sorted);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+
+    auto kern = k_varlen<V, METHOD, MIXED>;
+    constexpr size_t s64 = wpm_smem_per_matrix<V, 64, MIXED>();
+    constexpr size_t s32 = 2 * wpm_smem_per_matrix<V, 32, MIXED>();
+    const size_t smem = n_max > 32 ? s64 : (n_max > 16 ? s32 : 0);
+    static bool attr = false;
+    if (!attr) {
+        e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(s64 > s32 ? s64 : s32));
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, 64, smem) !=
+            hipSuccess || per_cu < 1)
+        per_cu = 1;
+    const int64_t grid = (int64_t)device_cus() * per_cu;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64), smem, s, (const V*)a, (V*)x, off_dev,
+                       sorted, plan, ns_steps, fill, info);
+    return hipGetLastError();
+}
+
+template <class V>
+static hipError_t varlen_dispatch(int64_t batch, const int32_t* n_dev, const int64_t* off_dev,
+                                  int n_max, const void* a, void* x, int method, int mixed,
+                                  int ns_steps, int fill, int32_t* info, void* work, hipStream_t s)
+{
+    constexpr bool f32 = sizeof(typename vt<V>::real) == 4;
+    if (mixed) {
+        if constexpr (f32) {
+            if (method == 0)
+                return varlen_run<V, 0, 1>(batch, n_dev, off_dev, n_max, a, x, ns_steps, fill, info, work, s);
+            return varlen_run<V, 1, 1>(batch, n_dev, off_dev, n_max, a, x, ns_steps, fill, info, work, s);
+        }
+        return hipErrorNotSupported;
+    }
+    if (method == 0)
+        return varlen_run<V, 0, 0>(batch, n_dev, off_dev, n_max, a, x, 0, fill, info, work, s);
+    return varlen_run<V, 1, 0>(batch, n_dev, off_dev, n_max, a, x, 0, fill, info, work, s);
+}
+
+}  // namespace ci

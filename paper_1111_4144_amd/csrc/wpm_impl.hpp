@@ -62,33 +62,26 @@ CI_D void pk_msub(V& acc, const Pk<V>& a, const Pk<V>& b)
     for (int c = 0; c < WPM_P<V>; ++c) msub(acc, a.v[c], b.v[c]);
 }
 
+// One matrix per group of NB lanes; `base` is the group's LDS area
+// (wpm_smem_per_matrix bytes), j the lane's column.  Every lane of the block
+// must call this together (it synchronises the block); `valid` only gates
+// global memory accesses.
 template <class V, int NB, int OP, int METHOD, int MIXED>
-__global__ void __launch_bounds__(64)
-k_wpm(const V* __restrict__ a, V* x, int64_t batch, int n, int64_t lda, int64_t sa, int64_t ldx,
-      int64_t sx, int ns_steps, int fill, int32_t* __restrict__ info,
-      typename vt<V>::real* __restrict__ dout)
+CI_D void wpm_matrix(const V* __restrict__ ab, V* xb, int n, bool valid, int64_t lda, int64_t ldx,
+                     int ns_steps, int fill, int32_t* info_b, typename vt<V>::real* dout_b,
+                     unsigned char* lds, int j)
 {
     using R = typename vt<V>::real;
     using W = typename vt<V>::wide;
-    constexpr int G = NB;
-    constexpr int MPB = 64 / G;                  // matrices per block (one wave)
     constexpr int P = WPM_P<V>;
     constexpr int LD = WPM_LD<V, NB>;
     constexpr int REG = NB * LD;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-
-    const int g = threadIdx.x / G;
-    const int j = threadIdx.x % G;               // owned column
-    const int64_t b = (int64_t)blockIdx.x * MPB + g;
-    const bool valid = b < batch;
     const int np = (n + P - 1) / P * P;          // padded order (identity)
-
-    V* base = reinterpret_cast<V*>(smem_raw + (size_t)g * wpm_smem_per_matrix<V, NB, MIXED>());
+    V* base = reinterpret_cast<V*>(lds);
     V* Am = MIXED ? base + 2 * REG : nullptr;
     V* Wm = base;
     V* Xm = base + REG;
     R* sv = reinterpret_cast<R*>(base + (MIXED ? 3 : 2) * REG);   // broadcast scalars
-    const V* ab = a + (valid ? b : 0) * sa;
     const V zero = mk<V>(R(0));
 
     // ---- load: column j of the Hermitian A (only the upper triangle is read),
@@ -181,12 +174,11 @@ k_wpm(const V* __restrict__ a, V* x, int64_t batch, int n, int64_t lda, int64_t 
 
     if constexpr (OP == OP_CHOL_FACTOR || OP == OP_LDL_FACTOR) {
         constexpr int J0 = (OP == OP_LDL_FACTOR) ? 1 : 0;
-        V* xb = x + (valid ? b : 0) * sx;
         if (valid && j < n) {
             for (int k = 0; k + J0 <= j; ++k) xb[k * ldx + j] = Wm[j * LD + k];
-            if constexpr (OP == OP_LDL_FACTOR) dout[b * n + j] = sv[NB + j];
+            if constexpr (OP == OP_LDL_FACTOR) dout_b[j] = sv[NB + j];
         }
-        if (valid && j == 0 && info) info[b] = fail;
+        if (valid && j == 0 && info_b) *info_b = fail;
         return;
     } else {
         // ---- Section IV back-substitution, rows i = np-1 .. 0 ----------------
@@ -224,7 +216,6 @@ k_wpm(const V* __restrict__ a, V* x, int64_t batch, int n, int64_t lda, int64_t 
             __syncthreads();
         }
 
-        V* xb = x + (valid ? b : 0) * sx;
         // ---- Newton-Schulz steps (mixed): E = I - A X into W (FP64 sums), then
         // X1 = X + X E, written straight to the output; later steps reload X.
         if (MIXED && ns_steps > 0) {
@@ -281,8 +272,28 @@ k_wpm(const V* __restrict__ a, V* x, int64_t batch, int n, int64_t lda, int64_t 
                 }
             }
         }
-        if (valid && j == 0 && info) info[b] = fail;
+        if (valid && j == 0 && info_b) *info_b = fail;
     }
+}
+
+template <class V, int NB, int OP, int METHOD, int MIXED>
+__global__ void __launch_bounds__(64)
+k_wpm(const V* __restrict__ a, V* x, int64_t batch, int n, int64_t lda, int64_t sa, int64_t ldx,
+      int64_t sx, int ns_steps, int fill, int32_t* __restrict__ info,
+      typename vt<V>::real* __restrict__ dout)
+{
+    constexpr int MPB = 64 / NB;                  // matrices per block (one wave)
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int g = threadIdx.x / NB;
+    const int j = threadIdx.x % NB;
+    const int64_t b = (int64_t)blockIdx.x * MPB + g;
+    const bool valid = b < batch;
+    const int64_t bb = valid ? b : 0;
+    wpm_matrix<V, NB, OP, METHOD, MIXED>(a + bb * sa, x + bb * sx, n, valid, lda, ldx, ns_steps,
+                                         fill, info ? info + bb : nullptr,
+                                         dout ? dout + bb * n : nullptr,
+                                         smem_raw + (size_t)g * wpm_smem_per_matrix<V, NB, MIXED>(),
+                                         j);
 }
 
 template <class V, int NB, int OP, int METHOD, int MIXED>

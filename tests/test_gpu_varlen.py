@@ -1,0 +1,122 @@
+"""GPU parity of the uneven-order batch path (one persistent launch after a
+device-side bucketing prologue) and of its HIP-graph capture."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1111_4144_amd import inputs as G
+from tests.helpers import TOL_FP32, TOL_FP64, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _unpack(packed, sizes, offs, b):
+    n = int(sizes[b])
+    return packed[offs[b]:offs[b] + n * n].reshape(n, n)
+
+
+def _check(xg, packed, sizes, offs, xo, tol, what):
+    worst = 0.0
+    for b in range(len(sizes)):
+        n = int(sizes[b])
+        if n == 0:
+            continue
+        x = _unpack(xg, sizes, offs, b).astype(np.float64)
+        ref = _unpack(xo, sizes, offs, b)
+        a = _unpack(packed, sizes, offs, b)
+        err = np.linalg.norm(x - ref) / np.linalg.norm(ref)
+        k = O.kappa2(a.astype(np.complex128)) if n <= 64 else 1.0
+        worst = max(worst, err / k)
+        assert err <= tol * k, "%s: matrix %d (n=%d) err %.3e kappa %.3e" % (what, b, n, err, k)
+    return worst
+
+
+@pytest.mark.parametrize("dtype,prec,ns,method", [
+    (np.float32, "plain", 0, "chol"), (np.float32, "mixed", 1, "chol"),
+    (np.float32, "mixed", 2, "ldl"), (np.float64, "plain", 0, "chol"),
+    (np.float64, "plain", 0, "ldl")])
+def test_varlen_matches_oracle(dtype, prec, ns, method):
+    t = torch_cuda()
+    from paper_1111_4144_amd import api
+    packed, sizes, offs = G.varlen_spd(3000, seed=21, dtype=dtype)
+    X, info = api.inverse_varlen(t.from_numpy(packed).cuda(), t.from_numpy(sizes).cuda(),
+                                 t.from_numpy(offs).cuda(), method=method, precision=prec,
+                                 ns_steps=ns, return_info=True)
+    t.cuda.synchronize()
+    xo, io = O.inv_prop_varlen(packed, sizes, offs, method)
+    assert np.array_equal(info.cpu().numpy(), io)
+    tol = TOL_FP64 if dtype == np.float64 else TOL_FP32
+    w = _check(X.cpu().numpy(), packed, sizes, offs, xo, tol, "varlen %s %s" % (prec, method))
+    print("max err/kappa %.3e" % w)
+
+
+def test_varlen_edge_cases():
+    """Orders 0 (nothing to do), 1, beyond n_max (info -1, X untouched), a
+    non-positive-definite matrix, and a bucket with a ragged tile."""
+    t = torch_cuda()
+    from paper_1111_4144_amd import api
+    sizes = np.array([0, 1, 5, 64, 40, 17, 9, 3, 33, 16, 8, 70 % 65], dtype=np.int32)
+    sizes[-1] = 50                                   # beyond n_max=48 below
+    offs = np.zeros(len(sizes), np.int64)
+    offs[1:] = np.cumsum(sizes.astype(np.int64) ** 2)[:-1]
+    rng = np.random.default_rng(4)
+    packed = np.zeros(int(offs[-1] + sizes[-1] ** 2), np.float64)
+    for b, n in enumerate(sizes):
+        if n:
+            packed[offs[b]:offs[b] + n * n] = G.random_hpd(rng, 1, int(n), complex_=False)[0].ravel()
+    bad = 4                                          # n = 40: make pivot 7 fail
+    m = _unpack(packed, sizes, offs, bad).copy()
+    m[:] = np.eye(40)
+    m[6, 6] = -1.0
+    packed[offs[bad]:offs[bad] + 1600] = m.ravel()
+    sizes_c = sizes.copy()
+    sizes_c[3] = 64
+    out = t.full((packed.size,), 5.0, dtype=t.float64, device="cuda")
+    X, info = api.inverse_varlen(t.from_numpy(packed).cuda(), t.from_numpy(sizes).cuda(),
+                                 t.from_numpy(offs).cuda(), n_max=64, out=out, return_info=True)
+    info = info.cpu().numpy()
+    x = X.cpu().numpy()
+    xo, io = O.inv_prop_varlen(packed, sizes, offs)
+    assert info[0] == 0 and info[bad] == 7 and np.all(np.isnan(_unpack(x, sizes, offs, bad)))
+    good = [b for b in range(len(sizes)) if sizes[b] and b != bad]
+    for b in good:
+        assert info[b] == 0
+        assert np.allclose(_unpack(x, sizes, offs, b), _unpack(xo, sizes, offs, b), rtol=1e-9, atol=1e-12)
+    # n_max = 48: the orders 64 and 50 are rejected with info -1 and left untouched
+    out2 = t.full((packed.size,), 5.0, dtype=t.float64, device="cuda")
+    X2, info2 = api.inverse_varlen(t.from_numpy(packed).cuda(), t.from_numpy(sizes).cuda(),
+                                   t.from_numpy(offs).cuda(), n_max=48, out=out2, return_info=True)
+    info2 = info2.cpu().numpy()
+    x2 = X2.cpu().numpy()
+    for b in (3, len(sizes) - 1):
+        assert info2[b] == -1
+        assert np.all(_unpack(x2, sizes, offs, b) == 5.0)
+
+
+def test_varlen_graph_capture_replays_match_eager():
+    t = torch_cuda()
+    from paper_1111_4144_amd import api
+    packed, sizes, offs = G.varlen_spd(2000, seed=22)
+    P = t.from_numpy(packed).cuda()
+    S = t.from_numpy(sizes).cuda()
+    F = t.from_numpy(offs).cuda()
+    eager = api.inverse_varlen(P, S, F, n_max=64, precision="mixed", ns_steps=1)
+    out = t.empty_like(P)
+    from paper_1111_4144_amd import _lib as L
+    import ctypes
+    ws = L.lib().chol_workspace_size(L.CI_FN_BATCHED, L.CI_F32, len(sizes), 0, None)
+    work = t.empty(ws, dtype=t.uint8, device="cuda")
+    s = t.cuda.Stream()
+    s.wait_stream(t.cuda.current_stream())
+    with t.cuda.stream(s):                            # warm-up outside the capture
+        api.inverse_varlen(P, S, F, n_max=64, precision="mixed", ns_steps=1, out=out, workspace=work)
+    t.cuda.current_stream().wait_stream(s)
+    g = t.cuda.CUDAGraph()
+    with t.cuda.graph(g):
+        api.inverse_varlen(P, S, F, n_max=64, precision="mixed", ns_steps=1, out=out, workspace=work)
+    for r in range(3):
+        out.fill_(float("nan"))
+        junk = api.inverse_varlen(P, S, F, n_max=64)   # eager work between replays
+        g.replay()
+        t.cuda.synchronize()
+        assert t.equal(out, eager), "replay %d differs from the eager result" % r
