@@ -39,15 +39,26 @@ def _sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
 
 
-def _newest_header():
-    hs = glob.glob(os.path.join(CSRC, "*.hpp")) + [os.path.join(INCLUDE, "cholinv.h")]
-    return max(os.path.getmtime(h) for h in hs)
+def _deps(path, seen=None):
+    """The source and every local header it includes (recursively)."""
+    import re
+    seen = set() if seen is None else seen
+    if path in seen or not os.path.exists(path):
+        return seen
+    seen.add(path)
+    with open(path) as f:
+        for inc in re.findall(r'#include\s+"([^"]+)"', f.read()):
+            for d in (CSRC, INCLUDE):
+                q = os.path.join(d, inc)
+                if os.path.exists(q):
+                    _deps(q, seen)
+    return seen
 
 
 def _compile(src, verbose, incremental=False):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     if incremental and os.path.exists(obj) and \
-            os.path.getmtime(obj) > max(os.path.getmtime(src), _newest_header()):
+            os.path.getmtime(obj) > max(os.path.getmtime(d) for d in _deps(src)):
         return obj
     cmd = [HIPCC, *CXXFLAGS, "-c", src, "-o", obj]
     if verbose:

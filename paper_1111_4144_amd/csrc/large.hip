@@ -1,0 +1,506 @@
+// large.hip -- X = A^{-1} for one real symmetric positive-definite matrix of
+// large order, blocked with MFMA GEMM tiles.
+//
+// Factorisation (Section II eqs. 3-4, right-looking, panels of nb rows):
+//   for each diagonal block I:
+//     R_II = chol(A_II) and R_II^{-1}          one workgroup, LDS resident
+//     R_I,>I = R_II^{-T} A_I,>I                 GEMM with the explicit inverse
+//     A_>I,>I -= R_I,>I^T R_I,>I                 upper-only GEMM (SYRK)
+// Inversion (Section IV in block form, block rows bottom-up).  Row block I of
+// R X = B, with B lower triangular and its upper triangle S = diag(1/r_ii)
+// known, gives for J > I:  X_I,J = -R_II^{-1} (R_I,>I X-hat_>I,J) (B_I,J = 0),
+// and for the diagonal block the scalar recurrence of the small kernels with
+// the extra term W = R_I,>I X-hat_>I,I = R_I,>I X_I,>I^T:
+//     x_ij = s_i (delta_ij s_i - w_ij - sum_{k>i, k in I} r_ik xh_kj).
+// Only the upper half of X is computed; the lower half is the mirror.
+//
+// Mixed precision: FP32 data and MFMA products; the diagonal pivots keep an
+// FP64 accumulator d_j = a_jj - sum_k r_kj^2 (updated per panel from the FP32
+// R entries, whose squares are exact in FP64); then Newton-Schulz steps
+// X <- X + X (I - A X) with the residual I - A X as an FP64 MFMA GEMM on the
+// exact FP32 inputs and the update as an FP32 GEMM.
+#include <algorithm>
+
+#include "ci_large.hpp"
+#include "ci_launch.hpp"
+#include "ci_types.hpp"
+#include "gemm_impl.hpp"
+
+namespace ci {
+
+template <class T> constexpr int LG_NB = sizeof(T) == 4 ? 128 : 64;   // panel width
+template <class T> constexpr int LG_P = 16 / (int)sizeof(T);
+template <class T> constexpr int LG_LD = LG_NB<T> + LG_P<T>;
+constexpr int LG_SPLIT_MAX = 8;
+
+// ---- diagonal block: Cholesky (Crout, FP64 pivots when mixed) + R^{-1} --------
+template <class T, int MIXED>
+__global__ void __launch_bounds__(LG_NB<T>)
+k_lg_diag_factor(T* __restrict__ W, int64_t ldw, int r0, int nl, const double* __restrict__ dacc,
+                 T* __restrict__ rinv, int32_t* __restrict__ info)
+{
+    constexpr int NB = LG_NB<T>, LD = LG_LD<T>, P = LG_P<T>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* Rm = reinterpret_cast<T*>(smem_raw);
+    T* Ym = Rm + NB * LD;
+    T* sv = Ym + NB * LD;                          // 1/r_ii, then a pivot flag
+    const int j = threadIdx.x;
+    T* Wb = W + (int64_t)r0 * ldw + r0;
+    for (int k = 0; k < NB; ++k) {
+        T v = (k == j) ? T(1) : T(0);
+        if (j < nl && k < nl && k <= j) v = Wb[(int64_t)k * ldw + j];
+        Rm[j * LD + k] = (k <= j) ? v : T(0);
+        Ym[j * LD + k] = T(0);
+    }
+    __syncthreads();
+    int fail = 0;
+    for (int i = 0; i < NB; ++i) {
+        const T* ci = Rm + i * LD;
+        const T* cj = Rm + j * LD;
+        T acc = cj[i];
+        double pd = (MIXED && i < nl) ? dacc[r0 + i] : (double)ci[i];
+        const int full = i / P;
+        for (int p = 0; p < full; ++p) {
+#pragma unroll
+            for (int c = 0; c < P; ++c) {
+                const T u = ci[p * P + c];
+                acc -= u * cj[p * P + c];
+                if (MIXED) pd -= (double)u * (double)u;
+            }
+        }
+        for (int k = full * P; k < i; ++k) {
+            const T u = ci[k];
+            acc -= u * cj[k];
+            if (MIXED) pd -= (double)u * (double)u;
+        }
+        __syncthreads();
+        if (j == i) {
+            const double piv = MIXED ? pd : (double)acc;
+            const bool ok = piv > 0.0 && piv < __builtin_inf();
+            const double r = sqrt(piv);
+            Rm[i * LD + i] = (T)r;
+            sv[i] = (T)(1.0 / r);
+            sv[NB] = ok ? T(1) : T(0);
+        }
+        __syncthreads();
+        if (!(sv[NB] > T(0)) && !fail && i < nl) fail = i + 1;
+        if (j > i) Rm[j * LD + i] = acc * sv[i];
+        __syncthreads();
+    }
+    if (j < nl)
+        for (int k = 0; k <= j; ++k) Wb[(int64_t)k * ldw + j] = Rm[j * LD + k];
+    // Y = R^{-1}, column j: y_jj = 1/r_jj, y_ij = -(1/r_ii) sum_{k=i+1..j} r_ik y_kj.
+    // Entries not computed yet are zero, and R is zero below its diagonal, so
+    // the packets may start below i+1.
+    Ym[j * LD + j] = sv[j];
+    for (int i = NB - 2; i >= 0; --i) {
+        if (i < j) {
+            T acc = T(0);
+            for (int p = (i + 1) / P; p <= j / P; ++p) {
+#pragma unroll
+                for (int c = 0; c < P; ++c) acc += Rm[(p * P + c) * LD + i] * Ym[j * LD + p * P + c];
+            }
+            Ym[j * LD + i] = -sv[i] * acc;
+        }
+    }
+    for (int i = 0; i < NB; ++i) rinv[(int64_t)i * NB + j] = (i <= j) ? Ym[j * LD + i] : T(0);
+    if (j == 0 && fail && info && info[0] == 0) info[0] = r0 + fail;
+}
+
+// ---- FP64 pivot accumulators: d_j -= sum_{k in panel} r_kj^2, j >= c0 ----------
+template <class T>
+__global__ void k_lg_dacc(const T* __restrict__ W, int64_t ldw, int r0, int nl, int c0, int n,
+                          double* __restrict__ dacc)
+{
+    const int j = c0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double s = dacc[j];
+    for (int k = 0; k < nl; ++k) {
+        const double v = (double)W[(int64_t)(r0 + k) * ldw + j];
+        s -= v * v;
+    }
+    dacc[j] = s;
+}
+
+template <class TI>
+__global__ void k_lg_dacc_init(const TI* __restrict__ a, int64_t lda, int n, double* __restrict__ dacc)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) dacc[j] = (double)a[(int64_t)j * lda + j];
+}
+
+// ---- diagonal block of X: the Section IV recurrence with the W term ------------
+template <class T>
+__global__ void __launch_bounds__(LG_NB<T>)
+k_lg_diag_inverse(const T* __restrict__ W, int64_t ldw, int r0, int nl,
+                  const T* __restrict__ wblk, int has_w, T* __restrict__ X, int64_t ldx)
+{
+    constexpr int NB = LG_NB<T>, LD = LG_LD<T>, P = LG_P<T>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* Rm = reinterpret_cast<T*>(smem_raw);
+    T* Xm = Rm + NB * LD;
+    T* sv = Xm + NB * LD;
+    const int j = threadIdx.x;
+    const T* Wb = W + (int64_t)r0 * ldw + r0;
+    for (int k = 0; k < NB; ++k) {
+        T v = T(0);
+        if (j < nl && k < nl && k <= j) v = Wb[(int64_t)k * ldw + j];
+        if (j >= nl && k == j) v = T(1);
+        Rm[j * LD + k] = v;
+        Xm[j * LD + k] = T(0);
+    }
+    __syncthreads();
+    sv[j] = T(1) / Rm[j * LD + j];
+    __syncthreads();
+    for (int i = nl - 1; i >= 0; --i) {
+        const T si = sv[i];
+        if (j > i && j < nl) {
+            T acc = has_w ? -wblk[(int64_t)i * NB + j] : T(0);
+            for (int p = (i + 1) / P; p < (nl + P - 1) / P; ++p) {
+#pragma unroll
+                for (int c = 0; c < P; ++c) acc -= Rm[(p * P + c) * LD + i] * Xm[j * LD + p * P + c];
+            }
+            const T xij = si * acc;
+            Xm[j * LD + i] = xij;
+            Xm[i * LD + j] = xij;
+        }
+        __syncthreads();
+        if (j == i) {
+            T d = si - (has_w ? wblk[(int64_t)i * NB + i] : T(0));
+            for (int p = (i + 1) / P; p < (nl + P - 1) / P; ++p) {
+#pragma unroll
+                for (int c = 0; c < P; ++c) d -= Rm[(p * P + c) * LD + i] * Xm[i * LD + p * P + c];
+            }
+            Xm[i * LD + i] = si * d;
+        }
+        __syncthreads();
+    }
+    if (j < nl)
+        for (int k = 0; k < nl; ++k) X[(int64_t)(r0 + k) * ldx + r0 + j] = Xm[j * LD + k];
+}
+
+// ---- split-K reduction: C = alpha * sum_s P_s (+ beta C) ------------------------
+template <class T>
+__global__ void k_lg_reduce(const T* __restrict__ part, int splits, int64_t pstride, int m, int n,
+                            int64_t ldp, T alpha, T* __restrict__ C, int64_t ldc)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)m * n) return;
+    const int i = (int)(e / n), jj = (int)(e % n);
+    T s = T(0);
+    for (int k = 0; k < splits; ++k) s += part[k * pstride + (int64_t)i * ldp + jj];
+    C[(int64_t)i * ldc + jj] = alpha * s;
+}
+
+// ---- transposed copy dst[j][i] = src[i][j] (32 x 32 tiles through LDS) ------------
+template <class TS, class TD>
+__global__ void k_lg_transpose(const TS* __restrict__ src, int64_t lds, TD* __restrict__ dst,
+                               int64_t ldd, int rows, int cols)
+{
+    __shared__ TD t[32][33];
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    for (int r = threadIdx.y; r < 32; r += blockDim.y) {
+        const int i = by + r, jj = bx + threadIdx.x;
+        if (i < rows && jj < cols) t[r][threadIdx.x] = (TD)src[(int64_t)i * lds + jj];
+    }
+    __syncthreads();
+    for (int r = threadIdx.y; r < 32; r += blockDim.y) {
+        const int jj = bx + r, i = by + threadIdx.x;
+        if (i < rows && jj < cols) dst[(int64_t)jj * ldd + i] = t[threadIdx.x][r];
+    }
+}
+
+// ---- symmetric matrix from its upper triangle: dst = upper(src) + mirror ---------
+template <class TS, class TD>
+__global__ void k_lg_symmetrize(const TS* __restrict__ src, int64_t lds, TD* __restrict__ dst,
+                                int64_t ldd, int n)
+{
+    __shared__ TD t[32][33];
+    const int bi = blockIdx.y, bj = blockIdx.x;
+    if (bj < bi) return;
+    const int i0 = bi * 32, j0 = bj * 32;
+    for (int r = threadIdx.y; r < 32; r += blockDim.y) {
+        const int i = i0 + r, jj = j0 + threadIdx.x;
+        TD v = TD(0);
+        if (i < n && jj < n && jj >= i) v = (TD)src[(int64_t)i * lds + jj];
+        t[r][threadIdx.x] = v;
+        if (i < n && jj < n && jj >= i) dst[(int64_t)i * ldd + jj] = v;
+    }
+    __syncthreads();
+    // mirror: dst[jj][i] = upper value (i < jj)
+    for (int r = threadIdx.y; r < 32; r += blockDim.y) {
+        const int jj = j0 + r, i = i0 + threadIdx.x;
+        if (i < n && jj < n && jj > i) dst[(int64_t)jj * ldd + i] = t[threadIdx.x][r];
+    }
+}
+
+template <class TS, class TD>
+__global__ void k_lg_copy(const TS* __restrict__ src, int64_t lds, TD* __restrict__ dst, int64_t ldd,
+                          int rows, int cols, int upper_only)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)rows * cols) return;
+    const int i = (int)(e / cols), jj = (int)(e % cols);
+    if (upper_only && jj < i) return;
+    dst[(int64_t)i * ldd + jj] = (TD)src[(int64_t)i * lds + jj];
+}
+
+template <class T>
+__global__ void k_lg_identity(T* __restrict__ e, int64_t lde, int n)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)n * n) return;
+    const int i = (int)(k / n), jj = (int)(k % n);
+    e[(int64_t)i * lde + jj] = (i == jj) ? T(1) : T(0);
+}
+
+template <class T>
+__global__ void k_lg_nan_if(const int32_t* __restrict__ info, T* __restrict__ x, int64_t ldx, int n)
+{
+    if (!info || info[0] == 0) return;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)n * n) return;
+    x[(k / n) * ldx + (k % n)] = (T)__builtin_nan("");
+}
+
+// ---- host orchestration ---------------------------------------------------------
+static unsigned blocks_for(int64_t count, int t = 256) { return (unsigned)((count + t - 1) / t); }
+
+template <class T>
+struct LgWork {
+    // byte offsets inside the caller's workspace
+    size_t wmat, rinv, ctmp, wblk, part, dacc, emat, xtmp, total;
+    LgWork(int64_t n, int mixed)
+    {
+        const int nb = LG_NB<T>;
+        const int64_t nblk = (n + nb - 1) / nb;
+        size_t o = 0;
+        auto take = [&](size_t bytes) { size_t r = o; o += (bytes + 255) / 256 * 256; return r; };
+        wmat = take((size_t)n * n * sizeof(T));
+        rinv = take((size_t)nblk * nb * nb * sizeof(T));
+        ctmp = take((size_t)nb * n * sizeof(T));
+        wblk = take((size_t)nb * nb * sizeof(T));
+        part = take((size_t)LG_SPLIT_MAX * nb * n * sizeof(T));
+        dacc = take((size_t)n * sizeof(double));
+        emat = mixed ? take((size_t)n * n * sizeof(double)) : 0;
+        xtmp = mixed ? take((size_t)n * n * sizeof(T)) : 0;
+        total = o;
+    }
+};
+
+template <class T, class TA, class TB>
+static hipError_t gemm(int M, int N, int K, double alpha, const TA* A, int64_t lda, int ta,
+                       const TB* B, int64_t ldb, int tb, double beta, T* C, int64_t ldc, int uplo,
+                       hipStream_t s)
+{
+    GemmArgs g{M, N, K, alpha, beta, A, lda, ta, B, ldb, tb, C, ldc, uplo};
+    return gemm_launch<T, TA, TB>(g, s);
+}
+
+// C (m x n) = alpha * A B with K split over `splits` partial products
+template <class T>
+static hipError_t gemm_splitk(int M, int N, int K, double alpha, const T* A, int64_t lda, int ta,
+                              const T* B, int64_t ldb, int tb, T* C, int64_t ldc, T* part,
+                              hipStream_t s)
+{
+    int splits = std::min(LG_SPLIT_MAX, std::max(1, K / 512));
+    const int tiles = ((M + GT_M - 1) / GT_M) * ((N + GT_N - 1) / GT_N);
+    if (tiles >= 512) splits = 1;
+    if (splits == 1) return gemm<T, T, T>(M, N, K, alpha, A, lda, ta, B, ldb, tb, 0.0, C, ldc, 0, s);
+    const int kc = (K + splits - 1) / splits;
+    splits = (K + kc - 1) / kc;            // every split has kc > 0 terms
+    const int64_t pstride = (int64_t)M * N;
+    for (int q = 0; q < splits; ++q) {
+        const int k0 = q * kc, kk = std::min(kc, K - k0);
+        const T* Aq = ta ? A + (int64_t)k0 * lda : A + k0;
+        const T* Bq = tb ? B + k0 : B + (int64_t)k0 * ldb;
+        hipError_t e = gemm<T, T, T>(M, N, kk, 1.0, Aq, lda, ta, Bq, ldb, tb, 0.0,
+                                     part + q * pstride, N, 0, s);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_lg_reduce<T>, dim3(blocks_for((int64_t)M * N)), dim3(256), 0, s, part,
+                       splits, pstride, M, N, (int64_t)N, (T)alpha, C, ldc);
+    return hipGetLastError();
+}
+
+template <class T, int MIXED>
+static hipError_t lg_factor(T* W, int64_t n, double* dacc, T* rinv, int32_t* info, hipStream_t s)
+{
+    constexpr int NB = LG_NB<T>;
+    const size_t smem = (size_t)(2 * NB * LG_LD<T> + NB + 4) * sizeof(T);
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_lg_diag_factor<T, MIXED>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    for (int64_t r0 = 0; r0 < n; r0 += NB) {
+        const int nl = (int)std::min<int64_t>(NB, n - r0);
+        const int64_t c0 = r0 + nl, mr = n - c0;
+        T* rv = rinv + (r0 / NB) * NB * NB;
+        hipLaunchKernelGGL((k_lg_diag_factor<T, MIXED>), dim3(1), dim3(NB), smem, s, W, n, (int)r0,
+                           nl, dacc, rv, info);
+        if (mr <= 0) break;
+        // R_I,>I = R_II^{-T} A_I,>I  (in place: one M tile spans the panel)
+        hipError_t e = gemm<T, T, T>(nl, (int)mr, nl, 1.0, rv, NB, 1, W + r0 * n + c0, n, 0, 0.0,
+                                     W + r0 * n + c0, n, 0, s);
+        if (e != hipSuccess) return e;
+        if (MIXED)
+            hipLaunchKernelGGL(k_lg_dacc<T>, dim3(blocks_for(mr)), dim3(256), 0, s, W, n, (int)r0,
+                               nl, (int)c0, (int)n, dacc);
+        // A_>I,>I -= R_I,>I^T R_I,>I  (upper half)
+        e = gemm<T, T, T>((int)mr, (int)mr, nl, -1.0, W + r0 * n + c0, n, 1, W + r0 * n + c0, n, 0,
+                          1.0, W + c0 * n + c0, n, 1, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipGetLastError();
+}
+
+template <class T>
+static hipError_t lg_inverse_from_r(const T* W, int64_t n, const T* rinv, T* X, int64_t ldx,
+                                    T* ctmp, T* wblk, T* part, hipStream_t s)
+{
+    constexpr int NB = LG_NB<T>;
+    const size_t smem = (size_t)(2 * NB * LG_LD<T> + NB + 4) * sizeof(T);
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_lg_diag_inverse<T>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const int64_t nblk = (n + NB - 1) / NB;
+    for (int64_t I = nblk - 1; I >= 0; --I) {
+        const int64_t r0 = I * NB;
+        const int nl = (int)std::min<int64_t>(NB, n - r0);
+        const int64_t c0 = r0 + nl, mr = n - c0;
+        const T* rv = rinv + I * NB * NB;
+        if (mr > 0) {
+            // C = R_I,>I X_>I,>I
+            hipError_t e = gemm_splitk<T>(nl, (int)mr, (int)mr, 1.0, W + r0 * n + c0, n, 0,
+                                          X + c0 * ldx + c0, ldx, 0, ctmp, mr, part, s);
+            if (e != hipSuccess) return e;
+            // X_I,>I = -R_II^{-1} C
+            e = gemm<T, T, T>(nl, (int)mr, nl, -1.0, rv, NB, 0, ctmp, mr, 0, 0.0,
+                              X + r0 * ldx + c0, ldx, 0, s);
+            if (e != hipSuccess) return e;
+            // X_>I,I = X_I,>I^T
+            hipLaunchKernelGGL((k_lg_transpose<T, T>), dim3((unsigned)((mr + 31) / 32), (unsigned)((nl + 31) / 32)),
+                               dim3(32, 8), 0, s, X + r0 * ldx + c0, ldx, X + c0 * ldx + r0, ldx,
+                               nl, (int)mr);
+            // W = R_I,>I X_I,>I^T
+            e = gemm_splitk<T>(nl, nl, (int)mr, 1.0, W + r0 * n + c0, n, 0, X + r0 * ldx + c0, ldx,
+                               1, wblk, NB, part, s);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL((k_lg_diag_inverse<T>), dim3(1), dim3(NB), smem, s, W, n, (int)r0, nl,
+                           wblk, mr > 0 ? 1 : 0, X, ldx);
+    }
+    return hipGetLastError();
+}
+
+template <class T, int MIXED>
+static hipError_t lg_inverse(int64_t n, const T* a, int64_t lda, T* x, int64_t ldx, int ns_steps,
+                             int32_t* info, void* work, hipStream_t s)
+{
+    LgWork<T> L(n, MIXED);
+    char* w = static_cast<char*>(work);
+    T* W = reinterpret_cast<T*>(w + L.wmat);
+    T* rinv = reinterpret_cast<T*>(w + L.rinv);
+    T* ctmp = reinterpret_cast<T*>(w + L.ctmp);
+    T* wblk = reinterpret_cast<T*>(w + L.wblk);
+    T* part = reinterpret_cast<T*>(w + L.part);
+    double* dacc = reinterpret_cast<double*>(w + L.dacc);
+    if (info) {
+        hipError_t e0 = fill_i32(info, 1, 0, s);
+        if (e0 != hipSuccess) return e0;
+    }
+    hipLaunchKernelGGL((k_lg_copy<T, T>), dim3(blocks_for(n * n)), dim3(256), 0, s, a, lda, W, n,
+                       (int)n, (int)n, 1);
+    if (MIXED)
+        hipLaunchKernelGGL(k_lg_dacc_init<T>, dim3(blocks_for(n)), dim3(256), 0, s, a, lda, (int)n,
+                           dacc);
+    hipError_t e = lg_factor<T, MIXED>(W, n, dacc, rinv, info, s);
+    if (e != hipSuccess) return e;
+    e = lg_inverse_from_r<T>(W, n, rinv, x, ldx, ctmp, wblk, part, s);
+    if (e != hipSuccess) return e;
+    if (MIXED && ns_steps > 0) {
+        double* E = reinterpret_cast<double*>(w + L.emat);
+        T* X1 = reinterpret_cast<T*>(w + L.xtmp);
+        // full symmetric A (the factor in W is no longer needed)
+        hipLaunchKernelGGL((k_lg_symmetrize<T, T>), dim3((unsigned)((n + 31) / 32), (unsigned)((n + 31) / 32)),
+                           dim3(32, 8), 0, s, a, lda, W, n, (int)n);
+        for (int st = 0; st < ns_steps; ++st) {
+            // E = I - A X in FP64 (FP32 operands, exact products)
+            hipLaunchKernelGGL(k_lg_identity<double>, dim3(blocks_for(n * n)), dim3(256), 0, s, E, n,
+                               (int)n);
+            e = gemm<double, T, T>((int)n, (int)n, (int)n, -1.0, W, n, 0, x, ldx, 0, 1.0, E, n, 0, s);
+            if (e != hipSuccess) return e;
+            // X1 = X + X E (upper half, FP32), then X = sym(X1)
+            hipLaunchKernelGGL((k_lg_copy<T, T>), dim3(blocks_for(n * n)), dim3(256), 0, s, x, ldx, X1,
+                               n, (int)n, (int)n, 1);
+            e = gemm<T, T, double>((int)n, (int)n, (int)n, 1.0, x, ldx, 0, E, n, 0, 1.0, X1, n, 1, s);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL((k_lg_symmetrize<T, T>), dim3((unsigned)((n + 31) / 32), (unsigned)((n + 31) / 32)),
+                               dim3(32, 8), 0, s, X1, n, x, ldx, (int)n);
+        }
+    }
+    if (info)
+        hipLaunchKernelGGL(k_lg_nan_if<T>, dim3(blocks_for(n * n)), dim3(256), 0, s, info, x, ldx,
+                           (int)n);
+    return hipGetLastError();
+}
+
+// ---- entry points ---------------------------------------------------------------
+size_t large_workspace(int dtype, int64_t n, int which, int mixed)
+{
+    (void)which;
+    if (dtype == DT_F32) return LgWork<float>(n, mixed).total;
+    if (dtype == DT_F64) return LgWork<double>(n, 0).total;
+    return 0;
+}
+
+hipError_t large_factor(int dtype, int64_t n, void* a, int64_t lda, int32_t* info, void* work,
+                        hipStream_t s)
+{
+    // in place on a (leading dimension lda must equal n for the blocked path)
+    if (lda != n) return hipErrorNotSupported;
+    if (info) {
+        hipError_t e0 = fill_i32(info, 1, 0, s);
+        if (e0 != hipSuccess) return e0;
+    }
+    if (dtype == DT_F32) {
+        LgWork<float> L(n, 0);
+        char* w = static_cast<char*>(work);
+        return lg_factor<float, 0>(static_cast<float*>(a), n, reinterpret_cast<double*>(w + L.dacc),
+                                   reinterpret_cast<float*>(w + L.rinv), info, s);
+    }
+    if (dtype == DT_F64) {
+        LgWork<double> L(n, 0);
+        char* w = static_cast<char*>(work);
+        return lg_factor<double, 0>(static_cast<double*>(a), n,
+                                    reinterpret_cast<double*>(w + L.dacc),
+                                    reinterpret_cast<double*>(w + L.rinv), info, s);
+    }
+    return hipErrorNotSupported;
+}
+
+hipError_t large_inverse(int dtype, int64_t n, const void* a, int64_t lda, void* x, int64_t ldx,
+                         int mixed, int ns_steps, int fill, int32_t* info, void* work, hipStream_t s)
+{
+    (void)fill;   // the blocked path always writes both halves (the GEMMs read them)
+    if (dtype == DT_F32) {
+        if (mixed)
+            return lg_inverse<float, 1>(n, static_cast<const float*>(a), lda, static_cast<float*>(x),
+                                        ldx, ns_steps, info, work, s);
+        return lg_inverse<float, 0>(n, static_cast<const float*>(a), lda, static_cast<float*>(x), ldx,
+                                    0, info, work, s);
+    }
+    if (dtype == DT_F64 && !mixed)
+        return lg_inverse<double, 0>(n, static_cast<const double*>(a), lda, static_cast<double*>(x),
+                                     ldx, 0, info, work, s);
+    return hipErrorNotSupported;
+}
+
+}  // namespace ci

@@ -1,4 +1,4 @@
-// stubs.hip -- entry points whose kernels are not built yet.
+// util.hip -- small utility kernels shared by the entry points.
 #include "ci_large.hpp"
 #include "ci_launch.hpp"
 
@@ -18,11 +18,5 @@ hipError_t fill_i32(int32_t* p, int64_t count, int32_t value, hipStream_t s)
     return hipGetLastError();
 }
 
-size_t large_workspace(int, int64_t, int, int) { return 0; }
-hipError_t large_factor(int, int64_t, void*, int64_t, int32_t*, void*, hipStream_t)
-{ return hipErrorNotSupported; }
-hipError_t large_inverse(int, int64_t, const void*, int64_t, void*, int64_t, int, int, int,
-                         int32_t*, void*, hipStream_t)
-{ return hipErrorNotSupported; }
 
 }  // namespace ci
