@@ -113,6 +113,101 @@ def cpu_baseline(target_seconds=10.0):
                       % (n_each, n_each, done // (2 * n_each), secs)}
 
 
+FP32_MFMA_PEAK = 157.3e12
+FP64_MFMA_PEAK = 78.6e12
+
+
+def large_workloads(torch, api, G, dev, steps):
+    """Single large SPD matrices, A = Q diag(lambda) Q^T, lambda log-spaced over
+    [1, 1e6]: FP32 + FP64 pivots at N=8192 (factor + inverse, then with one
+    Newton-Schulz step) and plain FP64 at N=4096.  Rates use the nominal N^3
+    flops of factor + inverse; a refinement step adds 2 N^3 (FP64) + N^3 (FP32)."""
+    out = {}
+    rng = np.random.default_rng(1)
+    for n, dt, prec, tag in [(8192, torch.float32, "mixed", "fp32_mixed_8192"),
+                             (4096, torch.float64, "plain", "fp64_plain_4096")]:
+        a, q, lam = G.large_spd(n, return_factors=True)
+        A = torch.from_numpy(a).to(dev).to(dt)
+        X = torch.empty_like(A)
+        ns_list = [0, 1] if prec == "mixed" else [0]
+        for ns in ns_list:
+            step_ms, _ = _time_loop(
+                torch, [lambda: api.inverse(A, precision=prec, ns_steps=ns, out=X)], steps, 1)
+            key = tag + ("_ns%d" % ns if prec == "mixed" else "")
+            out[key + "_ms"] = step_ms
+            out[key + "_tflops_n3"] = n ** 3 / (step_ms / 1e3) / 1e12
+            if ns == 0:
+                peak = FP32_MFMA_PEAK if dt == torch.float32 else FP64_MFMA_PEAK
+                out[key + "_mfma_frac"] = n ** 3 / (step_ms / 1e3) / peak
+            # sampled entries against the closed form Q diag(1/lambda) Q^T
+            idx = (rng.integers(0, n, 2048), rng.integers(0, n, 2048))
+            xs = X.cpu().numpy().astype(np.float64)[idx]
+            ref = np.einsum("sk,sk->s", q[idx[0]] / lam[None, :], q[idx[1]])
+            out[key + "_sampled_err_over_normX"] = float(np.abs(xs - ref).max() * lam.min())
+        del A, X
+        torch.cuda.empty_cache()
+    return out
+
+
+def varlen_workload(torch, api, G, O, dev, steps):
+    """262,144 real FP32 SPD matrices of orders U{2..64} in one packed buffer,
+    one persistent launch (device bucketing prologue included), eager and as a
+    replayed graph.  Bytes: A in + X out = 8 N^2 per matrix."""
+    packed, sizes, offsets = G.varlen_spd(262144)
+    P = torch.from_numpy(packed).to(dev)
+    S = torch.from_numpy(sizes).to(dev)
+    OF = torch.from_numpy(offsets).to(dev)
+    XV = torch.empty_like(P)
+    ws = torch.empty(api.varlen_workspace_bytes(P, S.shape[0]), dtype=torch.uint8, device=dev)
+
+    def call():
+        api.inverse_varlen(P, S, OF, n_max=64, out=XV, workspace=ws)
+
+    e_ms, _ = _time_loop(torch, [call], steps, 2)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        call()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            call()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g_ms, _ = _time_loop(torch, [g.replay], steps, 2)
+    count = sizes.shape[0]
+    nbytes = float(8 * np.sum(sizes.astype(np.int64) ** 2))
+    x = XV.cpu().numpy()
+    worst = 0.0
+    for b in range(0, count, count // 256):
+        n, o = int(sizes[b]), int(offsets[b])
+        am = packed[o:o + n * n].reshape(n, n).astype(np.float64)
+        xo, _ = O.inv_prop(am)
+        xm = x[o:o + n * n].reshape(n, n)
+        worst = max(worst, float(np.linalg.norm(xm - xo) / np.linalg.norm(xo)))
+    del P, S, OF, XV, ws
+    return {"varlen_eager_mat_per_s": count / (e_ms / 1e3),
+            "varlen_graph_mat_per_s": count / (g_ms / 1e3),
+            "varlen_graph_hbm_frac": nbytes / (g_ms / 1e3) / HBM_PEAK,
+            "varlen_graph_ms": g_ms,
+            "varlen_sampled_max_rel_err": worst}
+
+
+def plain_small_workload(torch, api, G, O, dev, steps):
+    """4096 complex128 4x4 matrices, plain FP64 (the oracle's own case): launch
+    time and error against the oracle."""
+    a = G.plain_fp64_4x4()
+    A = torch.from_numpy(a).to(dev)
+    X = torch.empty_like(A)
+    ms, _ = _time_loop(torch, [lambda: api.inverse(A, out=X)], steps * 10, 5)
+    xo, _ = O.inv_prop(a)
+    x = X.cpu().numpy()
+    err = np.sqrt(np.sum(np.abs(x - xo) ** 2, axis=(-1, -2))) / \
+        np.sqrt(np.sum(np.abs(xo) ** 2, axis=(-1, -2)))
+    return {"plain_c128_4x4_us_per_launch": ms * 1e3,
+            "plain_c128_4x4_max_rel_err": float(err.max())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,6 +215,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary workloads")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
+    ap.add_argument("--no-large", action="store_true", help="skip the N=8192 / N=4096 workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB three times (the reference "
                          "kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -244,6 +340,12 @@ def main():
             np.sqrt(np.sum(np.abs(want) ** 2, axis=(-1, -2)))
         details["grad16_max_rel_err"] = float(gerr.max())
         del AG, GG, XG
+
+    if not args.no_extras and not args.no_large:
+        details.update(large_workloads(torch, api, G, dev, max(2, args.steps // 4)))
+    if not args.no_extras:
+        details.update(varlen_workload(torch, api, G, O, dev, max(3, args.steps // 2)))
+        details.update(plain_small_workload(torch, api, G, O, dev, max(3, args.steps // 2)))
 
     line = {
         "metric": "inverses/s (8x8 c64 batch), TFLOP/s N=8192, fwd+bwd vs plain @ stated err",

@@ -7,6 +7,7 @@ on the GPU.  Calls are asynchronous on torch's current stream unless
 
 * ``inverse(A, method, precision, ns_steps)``   X = A^{-1} (Section IV)
 * ``inverse_varlen(packed, sizes, offsets)``    packed batch of uneven orders
+  (``varlen_workspace_bytes`` sizes its reusable workspace)
 * ``factor(A)`` / ``ldl(A)``                    Section II / II.A factorisations
 * ``inverse_backward(X, G)``                    gA = -X Gh X
 * ``CholInverse``                               autograd.Function saving X
@@ -78,11 +79,13 @@ def inverse(A: torch.Tensor, *, method="chol", precision="plain", ns_steps=None,
     if not A3.is_contiguous():
         A3 = A3.contiguous()
     B = A3.shape[0]
-    X = out if out is not None else torch.empty_like(A3)
     if out is not None:
         _check_device(out)
-        if out.shape != A3.shape or not out.is_contiguous() or out.dtype != A.dtype:
+        if out.shape != A.shape or not out.is_contiguous() or out.dtype != A.dtype:
             raise ValueError("out must be a contiguous tensor shaped like A")
+        X = out.view(-1, n, n)
+    else:
+        X = torch.empty_like(A3)
     info = torch.empty(B, dtype=torch.int32, device=A.device)   # every entry is written
     opts = L.make_opts(method, precision, ns_steps, fill_lower)
     dt = _dtype_code(A)
@@ -103,6 +106,13 @@ def inverse(A: torch.Tensor, *, method="chol", precision="plain", ns_steps=None,
     X = X.reshape(*batch_shape, n, n)
     info = info.reshape(batch_shape)
     return (X, info) if return_info else X
+
+
+def varlen_workspace_bytes(packed: torch.Tensor, batch: int) -> int:
+    """Workspace size (bytes) of ``inverse_varlen`` for ``batch`` matrices."""
+    opts = L.make_opts("chol", "plain", 0, True)
+    return int(L.lib().chol_workspace_size(L.CI_FN_BATCHED, _dtype_code(packed), batch, 0,
+                                           ctypes.byref(opts)))
 
 
 def inverse_varlen(packed: torch.Tensor, sizes: torch.Tensor, offsets: torch.Tensor, *,
