@@ -21,6 +21,12 @@ constexpr int TPM_BLOCK = 64;
 // Kernel variant request (autotuner / tests): 0 = automatic, 1 = load each
 // lane's matrix directly from HBM, 2 = one-shot LDS staging, 3 = persistent
 // pipelined LDS staging.
+// Engine of the Newton-Schulz refinement for order 9..16 groups: the lane
+// groups themselves (cross-lane broadcasts) or whole-wave MFMA products
+// (environment CHOLINV_NS_ENGINE=lanes|mfma, default mfma).
+enum { NS_ENGINE_MFMA = 0, NS_ENGINE_LANES = 1 };
+int ns_engine();
+
 enum { VARIANT_AUTO = 0, VARIANT_DIRECT = 1, VARIANT_STAGED = 2, VARIANT_PERSIST = 3 };
 
 // Compute units of the current device (cached).

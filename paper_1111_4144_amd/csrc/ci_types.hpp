@@ -125,6 +125,30 @@ template <> CI_D double nan_value<double>() { return __builtin_nan(""); }
 template <> CI_D cf     nan_value<cf>()     { return cf{__builtin_nanf(""), __builtin_nanf("")}; }
 template <> CI_D cd     nan_value<cd>()     { return cd{__builtin_nan(""), __builtin_nan("")}; }
 
+// r = sqrt(v), s = 1/sqrt(v) and s = 1/v from the hardware estimates
+// (v_rsq / v_rcp), for pivots whose results are used in FP32: the FP64 forms
+// (mixed precision: FP64 pivots, FP32 factors) add one Newton step, which
+// leaves an error far below FP32 rounding; the FP32 forms are within about
+// one FP32 ulp.  Non-positive or non-finite v give NaN or infinity (the
+// callers flag such pivots separately).
+CI_D void sqrt_rsqrt_est(double v, double& r, double& s)
+{
+    const double y = __builtin_amdgcn_rsq(v);
+    s = y * fma(-0.5 * v * y, y, 1.5);
+    r = v * s;
+}
+CI_D void sqrt_rsqrt_est(float v, float& r, float& s)
+{
+    s = __builtin_amdgcn_rsqf(v);
+    r = v * s;
+}
+CI_D double rcp_est(double v)
+{
+    const double y = __builtin_amdgcn_rcp(v);
+    return y * fma(-v, y, 2.0);
+}
+CI_D float rcp_est(float v) { return __builtin_amdgcn_rcpf(v); }
+
 CI_D bool pivot_ok(double v) { return v > 0.0 && v < __builtin_inf(); }
 CI_D bool pivot_ok(float v)  { return v > 0.f && v < __builtin_inff(); }
 

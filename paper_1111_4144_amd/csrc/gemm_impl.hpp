@@ -16,23 +16,18 @@
 // stage; the next stage's global loads are issued before the current stage's
 // MFMAs (register double buffering), LDS holds one stage.
 //
-// MFMA 16x16x4 lane layout (lane l = 0..63, g = l / 16, c = l % 16): the A
-// operand of lane l is A[c][k_g], the B operand B[k_g][c]; the four
-// accumulator values of lane l are D[4 g + v][c], v = 0..3, for the FP32
-// instruction and D[g + 4 v][c] for the FP64 one (measured).  Which physical k
-// goes to lane group g is free as long as A and B agree: lane group g takes
-// k = 4 g .. 4 g + 3 of the stage over the four MFMA steps, so each lane reads
-// 4 consecutive k values.
+// The MFMA operand and accumulator layouts are those of mfma.hpp; lane group
+// g takes k = 4 g .. 4 g + 3 of a stage over the four MFMA steps, so each
+// lane reads 4 consecutive k values.
 #pragma once
 
 #include <stdint.h>
 
 #include <hip/hip_runtime.h>
 
-namespace ci {
+#include "mfma.hpp"
 
-typedef float gf4 __attribute__((ext_vector_type(4)));
-typedef double gd4 __attribute__((ext_vector_type(4)));
+namespace ci {
 
 struct GemmArgs {
     int M, N, K;
@@ -50,25 +45,6 @@ struct GemmArgs {
 
 constexpr int GT_M = 128, GT_N = 128, GT_K = 16;
 constexpr int G_THREADS = 256;
-
-template <class T> struct mfma_acc;
-template <> struct mfma_acc<float> {
-    using type = gf4;
-    static __device__ __forceinline__ int row(int g, int v) { return 4 * g + v; }
-};
-template <> struct mfma_acc<double> {
-    using type = gd4;
-    static __device__ __forceinline__ int row(int g, int v) { return g + 4 * v; }
-};
-
-__device__ __forceinline__ gf4 mfma16(float a, float b, gf4 c)
-{
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ gd4 mfma16(double a, double b, gd4 c)
-{
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
 
 // LDS layouts: As[m][k] (k contiguous, row stride GT_K + PK) and Bs[n][k].
 template <class T> constexpr int G_PK = 16 / (int)sizeof(T);   // pad 16 bytes per row

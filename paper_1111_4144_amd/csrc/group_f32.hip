@@ -1,4 +1,5 @@
 // group_f32.hip -- register lane-group kernels (orders up to 16) for float elements.
+#include "group16_mfma.hpp"
 #include "group_impl.hpp"
 
 namespace ci {
@@ -6,7 +7,11 @@ namespace ci {
 hipError_t launch_group_f32(int n, int op, int method, int mixed, const BatchArgs& p,
                               hipStream_t s)
 {
-    if (n <= 16) return group_run_ops<float, 16, 16>(n, op, method, mixed, p, s);
+    if (n <= 16) {
+        if (op == OP_INV && mixed && ns_engine() == NS_ENGINE_MFMA)
+            return group16_mfma_run<float>(p, n, method, s);
+        return group_run_ops<float, 16, 16>(n, op, method, mixed, p, s);
+    }
     return launch_wpm_f32(n, op, method, mixed, p, s);
 }
 

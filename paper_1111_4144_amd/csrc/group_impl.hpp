@@ -118,46 +118,19 @@ template <class P> CI_D P dot_re(double a, double b) { return (P)(a * b); }
 template <class P> CI_D P dot_re(cf a, cf b) { return (P)a.re * (P)b.re + (P)a.im * (P)b.im; }
 template <class P> CI_D P dot_re(cd a, cd b) { return (P)(a.re * b.re + a.im * b.im); }
 
-// ---- one matrix per group ------------------------------------------------------
-// All G lanes of the group call this together (valid or not: the cross-lane
-// moves need every lane); `valid` only gates memory accesses.
-template <class V, int NB, int G, int OP, int METHOD, int MIXED>
-CI_D void group_matrix(const V* __restrict__ a, int64_t lda, int n, V* x, int64_t ldx, bool valid,
-                       int fill, int ns_steps, int q, int32_t* info_b,
-                       typename vt<V>::real* dout_b)
+// ---- factorisation and Section IV back-substitution on one group ----------------
+// On entry M[s][k] holds column j = s*G + q of A for k <= j (zero below) and
+// piv[s] its diagonal entry in the pivot precision P.  On return M holds
+// column j of R (factor operations) or of the Hermitian X-hat (OP_INV: x_kj
+// for k <= j, conj(x_jk) for k > j), and dall the LDL pivots.  Returns the
+// 1-based index of the first failing pivot (0 if none; beyond n for padding
+// is impossible since padded pivots are 1).
+template <class V, int NB, int G, int OP, int METHOD, int MIXED, int S, class P>
+CI_D int group_core(V (&M)[S][NB], P (&piv)[S], typename vt<V>::real (&dall)[NB], int q)
 {
     using R = typename vt<V>::real;
-    using W = typename vt<V>::wide;
-    using P = typename std::conditional<MIXED, double, R>::type;   // pivot precision
-    constexpr int S = (NB + G - 1) / G;                             // slots per lane
-
-    V M[S][NB];
-    V Af[MIXED ? S : 1][MIXED ? NB : 1];
-    P piv[S];
-#pragma unroll
-    for (int s = 0; s < S; ++s) piv[s] = P(1);
-    // ---- load column j = s*G + q (upper part from column j, lower part from
-    // row j, i.e. only the upper triangle of A is read); identity padding
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        const int j = s * G + q;
-#pragma unroll
-        for (int k = 0; k < NB; ++k) {
-            V v = mk<V>(R(k == j ? 1 : 0));
-            if (valid && j < n && k < n) {
-                v = (k <= j) ? a[k * lda + j] : cj(a[j * lda + k]);
-                if (k == j) v = realpart_only(v);
-            }
-            if constexpr (MIXED) Af[s][k] = v;
-            M[s][k] = (k <= j) ? v : mk<V>(R(0));
-            if (k == j) piv[s] = (P)re(v);
-        }
-    }
-
-    // ---- factorisation, right-looking ----------------------------------------
     int fail = 0;
     R sall[NB];     // 1/r_ii or 1/d_i, broadcast to every lane
-    R dall[NB];     // LDL pivots
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
         const int qi = i % G, si = i / G;
@@ -165,16 +138,25 @@ CI_D void group_matrix(const V* __restrict__ a, int64_t lda, int n, V* x, int64_
         const P pv = piv[si];
         bool ok;
         R rdiag, sinv, dval;
+        // results used in FP32 (mixed, or plain FP32) take the estimate forms
+        constexpr bool EST = MIXED || sizeof(R) == 4;
         if constexpr (METHOD == 0) {
             ok = pivot_ok(pv);
-            const P r = sqrt(pv);
-            rdiag = (R)r;
-            sinv = (R)(P(1) / r);
+            if constexpr (EST) {
+                P r, y;
+                sqrt_rsqrt_est(pv, r, y);
+                rdiag = (R)r;
+                sinv = (R)y;
+            } else {
+                const P r = sqrt(pv);
+                rdiag = (R)r;
+                sinv = (R)(P(1) / r);
+            }
             dval = rdiag;
         } else {
             ok = (OP == OP_LDL_FACTOR) ? (pv != P(0) && pv - pv == P(0)) : pivot_ok(pv);
             dval = (R)pv;
-            sinv = (R)(P(1) / pv);
+            sinv = EST ? (R)rcp_est(pv) : (R)(P(1) / pv);
             rdiag = R(1);
         }
         const int okb = bci<G>(ok ? 1 : 0, qi);
@@ -211,25 +193,7 @@ CI_D void group_matrix(const V* __restrict__ a, int64_t lda, int n, V* x, int64_
         __builtin_amdgcn_sched_barrier(0);   // bound live ranges between steps
     }
 
-    if constexpr (OP == OP_CHOL_FACTOR || OP == OP_LDL_FACTOR) {
-        constexpr int J0 = (OP == OP_LDL_FACTOR) ? 1 : 0;
-        if (valid) {
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-                const int j = s * G + q;
-                if (j < n) {
-#pragma unroll
-                    for (int k = 0; k < NB; ++k)
-                        if (k + J0 <= j && k < n) x[k * ldx + j] = M[s][k];
-                }
-            }
-            if constexpr (OP == OP_LDL_FACTOR) {
-#pragma unroll
-                for (int i = 0; i < NB; ++i)
-                    if (i % G == q && i < n) dout_b[i] = dall[i];
-            }
-        }
-    } else {
+    if constexpr (OP == OP_INV) {
         // ---- Section IV: rows i = NB-1 .. 0 of R X = S ------------------------
 #pragma unroll
         for (int i = NB - 1; i >= 0; --i) {
@@ -240,7 +204,12 @@ CI_D void group_matrix(const V* __restrict__ a, int64_t lda, int n, V* x, int64_
             for (int s = 0; s < S; ++s) acc[s] = mk<V>(R(0));
 #pragma unroll
             for (int k = i + 1; k < NB; ++k) {
-                const V rik = bc<G>(M[k / G][i], k % G);
+                // the same broadcast as in factor step i: without the empty asm
+                // on its source the compiler reuses that one and keeps all of
+                // R's broadcast rows live from the factorisation to here
+                V src = M[k / G][i];
+                opaque(src);
+                const V rik = bc<G>(src, k % G);
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
                     msub(acc[s], rik, M[s][k]);
@@ -261,7 +230,11 @@ CI_D void group_matrix(const V* __restrict__ a, int64_t lda, int n, V* x, int64_
             V d = mk<V>(sall[i]);
 #pragma unroll
             for (int k = i + 1; k < NB; ++k) {
-                const V rik = bc<G>(M[k / G][i], k % G);
+                // broadcast again rather than keep (a)'s broadcasts live across (b)
+                // (or the factorisation's)
+                V src = M[k / G][i];
+                opaque(src);
+                const V rik = bc<G>(src, k % G);
                 msub(d, rik, M[si][k]);
                 opaque(d);
             }
@@ -274,7 +247,67 @@ CI_D void group_matrix(const V* __restrict__ a, int64_t lda, int n, V* x, int64_
             }
             __builtin_amdgcn_sched_barrier(0);
         }
+    }
+    return fail;
+}
 
+// ---- one matrix per group ------------------------------------------------------
+// All G lanes of the group call this together (valid or not: the cross-lane
+// moves need every lane); `valid` only gates memory accesses.
+template <class V, int NB, int G, int OP, int METHOD, int MIXED>
+CI_D void group_matrix(const V* __restrict__ a, int64_t lda, int n, V* x, int64_t ldx, bool valid,
+                       int fill, int ns_steps, int q, int32_t* info_b,
+                       typename vt<V>::real* dout_b)
+{
+    using R = typename vt<V>::real;
+    using W = typename vt<V>::wide;
+    using P = typename std::conditional<MIXED, double, R>::type;   // pivot precision
+    constexpr int S = (NB + G - 1) / G;                             // slots per lane
+
+    V M[S][NB];
+    V Af[MIXED ? S : 1][MIXED ? NB : 1];
+    P piv[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) piv[s] = P(1);
+    // ---- load column j = s*G + q (upper part from column j, lower part from
+    // row j, i.e. only the upper triangle of A is read); identity padding
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int j = s * G + q;
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            V v = mk<V>(R(k == j ? 1 : 0));
+            if (valid && j < n && k < n) {
+                v = (k <= j) ? a[k * lda + j] : cj(a[j * lda + k]);
+                if (k == j) v = realpart_only(v);
+            }
+            if constexpr (MIXED) Af[s][k] = v;
+            M[s][k] = (k <= j) ? v : mk<V>(R(0));
+            if (k == j) piv[s] = (P)re(v);
+        }
+    }
+    R dall[NB];     // LDL pivots
+    const int fail = group_core<V, NB, G, OP, METHOD, MIXED>(M, piv, dall, q);
+
+    if constexpr (OP == OP_CHOL_FACTOR || OP == OP_LDL_FACTOR) {
+        constexpr int J0 = (OP == OP_LDL_FACTOR) ? 1 : 0;
+        if (valid) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int j = s * G + q;
+                if (j < n) {
+#pragma unroll
+                    for (int k = 0; k < NB; ++k)
+                        if (k + J0 <= j && k < n) x[k * ldx + j] = M[s][k];
+                }
+            }
+            if constexpr (OP == OP_LDL_FACTOR) {
+#pragma unroll
+                for (int i = 0; i < NB; ++i)
+                    if (i % G == q && i < n) dout_b[i] = dall[i];
+            }
+        }
+    } else {
         // ---- Newton-Schulz: X <- X + X(I - A X), residual in FP64 -------------
         // For every k: e_kj = delta_kj - sum_m a_km xh_mj (FP64, column k of A
         // from its owner; a_km = conj(a_mk)), then X E accumulates

@@ -24,6 +24,19 @@ int tpm_default_variant()
 
 void tpm_set_default_variant(int v) { g_variant = v; }
 
+namespace {
+int g_ns_engine = -1;
+}
+
+int ns_engine()
+{
+    if (g_ns_engine < 0) {
+        const char* e = std::getenv("CHOLINV_NS_ENGINE");
+        g_ns_engine = (e && std::strcmp(e, "lanes") == 0) ? NS_ENGINE_LANES : NS_ENGINE_MFMA;
+    }
+    return g_ns_engine;
+}
+
 int device_cus()
 {
     static int cus[64] = {0};

@@ -355,8 +355,9 @@ CI_D int tpm_body(V (&A)[N][N], const Out& out, int ns_steps, bool vec_full_stor
 #pragma unroll
                 for (int k = 0; k < i; ++k) rad = sub_abs2_d(rad, Rm[k][i]);
                 if (!pivot_ok(rad) && !fail) fail = i + 1;
-                const double r = sqrt(rad);
-                s[i] = (R)(1.0 / r);
+                double r, y;
+                sqrt_rsqrt_est(rad, r, y);
+                s[i] = (R)y;
                 Rm[i][i] = mk<V>((R)r);
             } else {
                 R rad = re(A[i][i]);
@@ -389,7 +390,7 @@ CI_D int tpm_body(V (&A)[N][N], const Out& out, int ns_steps, bool vec_full_stor
                 for (int k = 0; k < i; ++k) di = fma(-dd[k], abs2_d(Rm[k][i]), di);
                 dd[i] = di;
                 di_r = (R)di;
-                s[i] = (R)(1.0 / di);
+                s[i] = (R)rcp_est(di);
                 ok = (OP == OP_LDL_FACTOR) ? (di != 0.0 && di - di == 0.0) : pivot_ok(di);
             } else {
                 R di = re(A[i][i]);
