@@ -93,8 +93,10 @@ def build(jobs: int | None = None, verbose: bool = False, incremental: bool = Fa
 
 
 def source_digest() -> str:
+    """Digest of every kernel source and header (ties measured counters to code)."""
     h = hashlib.sha256()
-    for s in _sources() + [os.path.join(INCLUDE, "cholinv.h")]:
+    for s in _sources() + sorted(glob.glob(os.path.join(CSRC, "*.hpp"))) + \
+            [os.path.join(INCLUDE, "cholinv.h")]:
         with open(s, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
