@@ -33,6 +33,52 @@ template <class T> constexpr int LG_P = 16 / (int)sizeof(T);
 template <class T> constexpr int LG_LD = LG_NB<T> + LG_P<T>;
 constexpr int LG_SPLIT_MAX = 8;
 
+// sum over packets p in [p0, p1) of sum_c a_p[c] b_p[c]; fa / fb fetch the P
+// entries of packet p.  Four packets are fetched before their products so
+// that several LDS loads are in flight; P independent partial sums.
+template <class T, class FA, class FB>
+__device__ __forceinline__ T lg_dot(int p0, int p1, FA fa, FB fb)
+{
+    constexpr int P = LG_P<T>;
+    T part[P];
+#pragma unroll
+    for (int c = 0; c < P; ++c) part[c] = T(0);
+    int p = p0;
+    for (; p + 4 <= p1; p += 4) {
+        T a[4][P], b[4][P];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            fa(p + q, a[q]);
+            fb(p + q, b[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < P; ++c) part[c] += a[q][c] * b[q][c];
+    }
+    for (; p < p1; ++p) {
+        T a[P], b[P];
+        fa(p, a);
+        fb(p, b);
+#pragma unroll
+        for (int c = 0; c < P; ++c) part[c] += a[c] * b[c];
+    }
+    T r = part[0];
+#pragma unroll
+    for (int c = 1; c < P; ++c) r += part[c];
+    return r;
+}
+
+// contiguous packet of P entries from LDS (16 bytes, aligned)
+template <class T>
+__device__ __forceinline__ void lg_ldv(const T* q, T (&v)[LG_P<T>])
+{
+    typedef T v16 __attribute__((ext_vector_type(LG_P<T>)));
+    const v16 w = *reinterpret_cast<const v16*>(q);
+#pragma unroll
+    for (int c = 0; c < LG_P<T>; ++c) v[c] = w[c];
+}
+
 // ---- diagonal block: Cholesky (Crout, FP64 pivots when mixed) + R^{-1} --------
 template <class T, int MIXED>
 __global__ void __launch_bounds__(LG_NB<T>)
@@ -54,28 +100,21 @@ k_lg_diag_factor(T* __restrict__ W, int64_t ldw, int r0, int nl, const double* _
     }
     __syncthreads();
     int fail = 0;
+    // FP64 sum of squares of column j of R above the diagonal, accumulated as
+    // its entries are produced (the pivot of step j is dacc_j minus it)
+    double sq = 0.0;
     for (int i = 0; i < NB; ++i) {
         const T* ci = Rm + i * LD;
         const T* cj = Rm + j * LD;
-        T acc = cj[i];
-        double pd = (MIXED && i < nl) ? dacc[r0 + i] : (double)ci[i];
+        // a_ij - sum_{k<i} r_ki r_kj: whole packets, then the partial one
         const int full = i / P;
-        for (int p = 0; p < full; ++p) {
-#pragma unroll
-            for (int c = 0; c < P; ++c) {
-                const T u = ci[p * P + c];
-                acc -= u * cj[p * P + c];
-                if (MIXED) pd -= (double)u * (double)u;
-            }
-        }
-        for (int k = full * P; k < i; ++k) {
-            const T u = ci[k];
-            acc -= u * cj[k];
-            if (MIXED) pd -= (double)u * (double)u;
-        }
+        T dot = lg_dot<T>(0, full, [&](int p, T (&v)[P]) { lg_ldv(ci + p * P, v); },
+                          [&](int p, T (&v)[P]) { lg_ldv(cj + p * P, v); });
+        for (int k = full * P; k < i; ++k) dot += ci[k] * cj[k];
+        const T acc = cj[i] - dot;
         __syncthreads();
         if (j == i) {
-            const double piv = MIXED ? pd : (double)acc;
+            const double piv = MIXED ? ((i < nl ? dacc[r0 + i] : 1.0) - sq) : (double)acc;
             const bool ok = piv > 0.0 && piv < __builtin_inf();
             const double r = sqrt(piv);
             Rm[i * LD + i] = (T)r;
@@ -84,7 +123,11 @@ k_lg_diag_factor(T* __restrict__ W, int64_t ldw, int r0, int nl, const double* _
         }
         __syncthreads();
         if (!(sv[NB] > T(0)) && !fail && i < nl) fail = i + 1;
-        if (j > i) Rm[j * LD + i] = acc * sv[i];
+        if (j > i) {
+            const T rij = acc * sv[i];
+            Rm[j * LD + i] = rij;
+            if (MIXED) sq = fma((double)rij, (double)rij, sq);
+        }
         __syncthreads();
     }
     if (j < nl)
@@ -95,11 +138,14 @@ k_lg_diag_factor(T* __restrict__ W, int64_t ldw, int r0, int nl, const double* _
     Ym[j * LD + j] = sv[j];
     for (int i = NB - 2; i >= 0; --i) {
         if (i < j) {
-            T acc = T(0);
-            for (int p = (i + 1) / P; p <= j / P; ++p) {
+            // row i of R is strided in this column-major layout
+            const T acc = lg_dot<T>(
+                (i + 1) / P, j / P + 1,
+                [&](int p, T (&v)[P]) {
 #pragma unroll
-                for (int c = 0; c < P; ++c) acc += Rm[(p * P + c) * LD + i] * Ym[j * LD + p * P + c];
-            }
+                    for (int c = 0; c < P; ++c) v[c] = Rm[(p * P + c) * LD + i];
+                },
+                [&](int p, T (&v)[P]) { lg_ldv(Ym + j * LD + p * P, v); });
             Ym[j * LD + i] = -sv[i] * acc;
         }
     }
@@ -142,36 +188,35 @@ k_lg_diag_inverse(const T* __restrict__ W, int64_t ldw, int r0, int nl,
     T* sv = Xm + NB * LD;
     const int j = threadIdx.x;
     const T* Wb = W + (int64_t)r0 * ldw + r0;
+    // R row major here (Rm[k * LD + j] = r_kj): the dot products below run
+    // along rows of R and columns of X, both contiguous
     for (int k = 0; k < NB; ++k) {
         T v = T(0);
         if (j < nl && k < nl && k <= j) v = Wb[(int64_t)k * ldw + j];
         if (j >= nl && k == j) v = T(1);
-        Rm[j * LD + k] = v;
+        Rm[k * LD + j] = v;
         Xm[j * LD + k] = T(0);
     }
     __syncthreads();
     sv[j] = T(1) / Rm[j * LD + j];
     __syncthreads();
+    const int pend = (nl + P - 1) / P;
     for (int i = nl - 1; i >= 0; --i) {
         const T si = sv[i];
         if (j > i && j < nl) {
-            T acc = has_w ? -wblk[(int64_t)i * NB + j] : T(0);
-            for (int p = (i + 1) / P; p < (nl + P - 1) / P; ++p) {
-#pragma unroll
-                for (int c = 0; c < P; ++c) acc -= Rm[(p * P + c) * LD + i] * Xm[j * LD + p * P + c];
-            }
-            const T xij = si * acc;
+            const T dot = lg_dot<T>((i + 1) / P, pend,
+                                    [&](int p, T (&v)[P]) { lg_ldv(Rm + i * LD + p * P, v); },
+                                    [&](int p, T (&v)[P]) { lg_ldv(Xm + j * LD + p * P, v); });
+            const T xij = si * ((has_w ? -wblk[(int64_t)i * NB + j] : T(0)) - dot);
             Xm[j * LD + i] = xij;
             Xm[i * LD + j] = xij;
         }
         __syncthreads();
         if (j == i) {
-            T d = si - (has_w ? wblk[(int64_t)i * NB + i] : T(0));
-            for (int p = (i + 1) / P; p < (nl + P - 1) / P; ++p) {
-#pragma unroll
-                for (int c = 0; c < P; ++c) d -= Rm[(p * P + c) * LD + i] * Xm[i * LD + p * P + c];
-            }
-            Xm[i * LD + i] = si * d;
+            const T dot = lg_dot<T>((i + 1) / P, pend,
+                                    [&](int p, T (&v)[P]) { lg_ldv(Rm + i * LD + p * P, v); },
+                                    [&](int p, T (&v)[P]) { lg_ldv(Xm + i * LD + p * P, v); });
+            Xm[i * LD + i] = si * (si - (has_w ? wblk[(int64_t)i * NB + i] : T(0)) - dot);
         }
         __syncthreads();
     }
@@ -270,6 +315,7 @@ template <class T>
 struct LgWork {
     // byte offsets inside the caller's workspace
     size_t wmat, rinv, ctmp, wblk, part, dacc, emat, xtmp, total;
+    int64_t part_elems;
     LgWork(int64_t n, int mixed)
     {
         const int nb = LG_NB<T>;
@@ -280,7 +326,8 @@ struct LgWork {
         rinv = take((size_t)nblk * nb * nb * sizeof(T));
         ctmp = take((size_t)nb * n * sizeof(T));
         wblk = take((size_t)nb * nb * sizeof(T));
-        part = take((size_t)LG_SPLIT_MAX * nb * n * sizeof(T));
+        part_elems = (int64_t)LG_SPLIT_MAX * nb * n;
+        part = take((size_t)part_elems * sizeof(T));
         dacc = take((size_t)n * sizeof(double));
         emat = mixed ? take((size_t)n * n * sizeof(double)) : 0;
         xtmp = mixed ? take((size_t)n * n * sizeof(T)) : 0;
@@ -297,27 +344,29 @@ static hipError_t gemm(int M, int N, int K, double alpha, const TA* A, int64_t l
     return gemm_launch<T, TA, TB>(g, s);
 }
 
-// C (m x n) = alpha * A B with K split over `splits` partial products
+// C (m x n) = alpha * A B with K split over partial products so that about
+// 512 workgroups run (two per CU), each split at least 64 deep, the partials
+// within the workspace's capacity `cap` (elements)
 template <class T>
 static hipError_t gemm_splitk(int M, int N, int K, double alpha, const T* A, int64_t lda, int ta,
                               const T* B, int64_t ldb, int tb, T* C, int64_t ldc, T* part,
-                              hipStream_t s)
+                              int64_t cap, hipStream_t s)
 {
-    int splits = std::min(LG_SPLIT_MAX, std::max(1, K / 512));
     const int tiles = ((M + GT_M - 1) / GT_M) * ((N + GT_N - 1) / GT_N);
-    if (tiles >= 512) splits = 1;
-    if (splits == 1) return gemm<T, T, T>(M, N, K, alpha, A, lda, ta, B, ldb, tb, 0.0, C, ldc, 0, s);
-    const int kc = (K + splits - 1) / splits;
+    int splits = (512 + tiles - 1) / tiles;
+    splits = std::min<int64_t>(splits, std::max(1, K / 64));
+    splits = (int)std::min<int64_t>(splits, cap / ((int64_t)M * N));
+    if (splits <= 1) return gemm<T, T, T>(M, N, K, alpha, A, lda, ta, B, ldb, tb, 0.0, C, ldc, 0, s);
+    constexpr int BK = G_BK<T>;
+    const int kc = ((K + splits - 1) / splits + BK - 1) / BK * BK;   // whole stages
     splits = (K + kc - 1) / kc;            // every split has kc > 0 terms
     const int64_t pstride = (int64_t)M * N;
-    for (int q = 0; q < splits; ++q) {
-        const int k0 = q * kc, kk = std::min(kc, K - k0);
-        const T* Aq = ta ? A + (int64_t)k0 * lda : A + k0;
-        const T* Bq = tb ? B + k0 : B + (int64_t)k0 * ldb;
-        hipError_t e = gemm<T, T, T>(M, N, kk, 1.0, Aq, lda, ta, Bq, ldb, tb, 0.0,
-                                     part + q * pstride, N, 0, s);
-        if (e != hipSuccess) return e;
-    }
+    GemmArgs g{M, N, K, 1.0, 0.0, A, lda, ta, B, ldb, tb, part, (int64_t)N, 0};
+    g.splits = splits;
+    g.kc = kc;
+    g.cstride = pstride;
+    hipError_t e = gemm_launch<T, T, T>(g, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_lg_reduce<T>, dim3(blocks_for((int64_t)M * N)), dim3(256), 0, s, part,
                        splits, pstride, M, N, (int64_t)N, (T)alpha, C, ldc);
     return hipGetLastError();
@@ -359,7 +408,7 @@ static hipError_t lg_factor(T* W, int64_t n, double* dacc, T* rinv, int32_t* inf
 
 template <class T>
 static hipError_t lg_inverse_from_r(const T* W, int64_t n, const T* rinv, T* X, int64_t ldx,
-                                    T* ctmp, T* wblk, T* part, hipStream_t s)
+                                    T* ctmp, T* wblk, T* part, int64_t part_cap, hipStream_t s)
 {
     constexpr int NB = LG_NB<T>;
     const size_t smem = (size_t)(2 * NB * LG_LD<T> + NB + 4) * sizeof(T);
@@ -379,7 +428,7 @@ static hipError_t lg_inverse_from_r(const T* W, int64_t n, const T* rinv, T* X, 
         if (mr > 0) {
             // C = R_I,>I X_>I,>I
             hipError_t e = gemm_splitk<T>(nl, (int)mr, (int)mr, 1.0, W + r0 * n + c0, n, 0,
-                                          X + c0 * ldx + c0, ldx, 0, ctmp, mr, part, s);
+                                          X + c0 * ldx + c0, ldx, 0, ctmp, mr, part, part_cap, s);
             if (e != hipSuccess) return e;
             // X_I,>I = -R_II^{-1} C
             e = gemm<T, T, T>(nl, (int)mr, nl, -1.0, rv, NB, 0, ctmp, mr, 0, 0.0,
@@ -391,7 +440,7 @@ static hipError_t lg_inverse_from_r(const T* W, int64_t n, const T* rinv, T* X, 
                                nl, (int)mr);
             // W = R_I,>I X_I,>I^T
             e = gemm_splitk<T>(nl, nl, (int)mr, 1.0, W + r0 * n + c0, n, 0, X + r0 * ldx + c0, ldx,
-                               1, wblk, NB, part, s);
+                               1, wblk, NB, part, part_cap, s);
             if (e != hipSuccess) return e;
         }
         hipLaunchKernelGGL((k_lg_diag_inverse<T>), dim3(1), dim3(NB), smem, s, W, n, (int)r0, nl,
@@ -423,7 +472,7 @@ static hipError_t lg_inverse(int64_t n, const T* a, int64_t lda, T* x, int64_t l
                            dacc);
     hipError_t e = lg_factor<T, MIXED>(W, n, dacc, rinv, info, s);
     if (e != hipSuccess) return e;
-    e = lg_inverse_from_r<T>(W, n, rinv, x, ldx, ctmp, wblk, part, s);
+    e = lg_inverse_from_r<T>(W, n, rinv, x, ldx, ctmp, wblk, part, L.part_elems, s);
     if (e != hipSuccess) return e;
     if (MIXED && ns_steps > 0) {
         double* E = reinterpret_cast<double*>(w + L.emat);

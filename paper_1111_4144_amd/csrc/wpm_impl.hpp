@@ -48,6 +48,27 @@ CI_D Pk<V> ldpk(const V* p)
     return r;
 }
 
+// Loop over packets [p0, p1): fetch(p, u, w) loads the two operand packets,
+// body(p, u, w) consumes them.  Four packets are fetched before their bodies
+// run, so several LDS loads are in flight at once.
+template <class V, class F, class B>
+CI_D void pk_loop(int p0, int p1, F fetch, B body)
+{
+    int p = p0;
+    for (; p + 4 <= p1; p += 4) {
+        Pk<V> u[4], w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) fetch(p + q, u[q], w[q]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) body(p + q, u[q], w[q]);
+    }
+    for (; p < p1; ++p) {
+        Pk<V> u, w;
+        fetch(p, u, w);
+        body(p, u, w);
+    }
+}
+
 // acc -= sum over the packet of conj(a) * b   (P-length partial dot)
 template <class V>
 CI_D void pk_msubc(V& acc, const Pk<V>& a, const Pk<V>& b)
@@ -102,42 +123,37 @@ CI_D void wpm_matrix(const V* __restrict__ ab, V* xb, int n, bool valid, int64_t
     // W column j holds r_kj for k < i and the untouched a_kj for k >= i, so
     // the sums must stop at i: the last packet is masked)
     int fail = 0;
+    // mixed: FP64 sum over completed rows k of |r_kj|^2 (Cholesky) or
+    // d_k |r_kj|^2 (LDL), accumulated as lane j produces r_kj; the pivot of
+    // row j is re(a_jj) minus it
+    double sq = 0.0;
     for (int i = 0; i < np; ++i) {
         const V* ci_ = Wm + i * LD;     // column i
         const V* cj_ = Wm + j * LD;     // column j
         V acc = cj_[i];                 // a_ij (j >= i)
-        double pd = (double)re(ci_[i]); // pivot radicand / d_i in FP64
         const int full = i / P;
-        for (int p = 0; p < full; ++p) {
-            const Pk<V> u = ldpk(ci_ + p * P);
-            const Pk<V> w = ldpk(cj_ + p * P);
-            if constexpr (METHOD == 0) {
-                pk_msubc(acc, u, w);
-                if constexpr (MIXED) {
+        pk_loop<V>(
+            0, full,
+            [&](int p, Pk<V>& u, Pk<V>& w) {
+                u = ldpk(ci_ + p * P);
+                w = ldpk(cj_ + p * P);
+            },
+            [&](int p, const Pk<V>& u, const Pk<V>& w) {
+                if constexpr (METHOD == 0) {
+                    pk_msubc(acc, u, w);
+                } else {
+                    // LDL: sum conj(r_ki) d_k r_kj with d_k in sv[NB + k]
 #pragma unroll
-                    for (int c = 0; c < P; ++c) pd = sub_abs2_d(pd, u.v[c]);
+                    for (int c = 0; c < P; ++c)
+                        msubc(acc, scal(u.v[c], sv[NB + p * P + c]), w.v[c]);
                 }
-            } else {
-                // LDL: sum conj(r_ki) d_k r_kj with d_k in sv[NB + k]
-#pragma unroll
-                for (int c = 0; c < P; ++c) {
-                    const R dk = sv[NB + p * P + c];
-                    msubc(acc, scal(u.v[c], dk), w.v[c]);
-                    if constexpr (MIXED) pd = fma(-(double)dk, abs2_d(u.v[c]), pd);
-                }
-            }
-        }
+            });
         for (int k = full * P; k < i; ++k) {
             const V u = ci_[k];
-            if constexpr (METHOD == 0) {
-                msubc(acc, u, cj_[k]);
-                if constexpr (MIXED) pd = sub_abs2_d(pd, u);
-            } else {
-                const R dk = sv[NB + k];
-                msubc(acc, scal(u, dk), cj_[k]);
-                if constexpr (MIXED) pd = fma(-(double)dk, abs2_d(u), pd);
-            }
+            if constexpr (METHOD == 0) msubc(acc, u, cj_[k]);
+            else msubc(acc, scal(u, sv[NB + k]), cj_[k]);
         }
+        const double pd = (double)re(cj_[i]) - sq;   // meaningful on lane i only
         // lane i owns the pivot: FP64 when mixed, else the compute precision
         const R prc = MIXED ? (R)pd : re(acc);
         __syncthreads();                       // every lane has read row i inputs
@@ -168,7 +184,14 @@ CI_D void wpm_matrix(const V* __restrict__ ab, V* xb, int n, bool valid, int64_t
         }
         __syncthreads();
         if (!(sv[2 * NB] > R(0)) && !fail) fail = i + 1;
-        if (j > i) Wm[j * LD + i] = scal(acc, sv[i]);   // r_ij
+        if (j > i) {
+            const V rij = scal(acc, sv[i]);
+            Wm[j * LD + i] = rij;
+            if constexpr (MIXED) {
+                if constexpr (METHOD == 0) sq += abs2_d(rij);
+                else sq = fma((double)sv[NB + i], abs2_d(rij), sq);
+            }
+        }
         __syncthreads();
     }
 
@@ -182,19 +205,27 @@ CI_D void wpm_matrix(const V* __restrict__ ab, V* xb, int n, bool valid, int64_t
         return;
     } else {
         // ---- Section IV back-substitution, rows i = np-1 .. 0 ----------------
+        // Row i of R is copied into the unused lower part of column i of W
+        // (W[i][k] = r_ik for k > i), so both operands below are contiguous
+        // packets.  Entries k <= i of that column still hold R's column i, but
+        // they meet rows <= i of X, which are zero until row i is produced.
+        for (int k = 0; k < j; ++k) Wm[k * LD + j] = Wm[j * LD + k];
+        __syncthreads();
         for (int i = np - 1; i >= 0; --i) {
             const R si = sv[i];
+            const V* ri = Wm + i * LD;
+            const int p0 = (i + 1) / P;
             if (j > i) {
-                // x_ij = -s_i sum_{k>i} r_ik xh_kj  (LDL: without s_i); r_ik is row
-                // i of R = entry i of column k; X column j is zero for rows <= i
+                // x_ij = -s_i sum_{k>i} r_ik xh_kj  (LDL: without s_i)
                 V acc = zero;
                 const V* xc = Xm + j * LD;
-                const int p0 = (i + 1) / P;
-                for (int p = p0; p < np / P; ++p) {
-                    const Pk<V> w = ldpk(xc + p * P);
-#pragma unroll
-                    for (int c = 0; c < P; ++c) msub(acc, Wm[(p * P + c) * LD + i], w.v[c]);
-                }
+                pk_loop<V>(
+                    p0, np / P,
+                    [&](int p, Pk<V>& u, Pk<V>& w) {
+                        u = ldpk(ri + p * P);
+                        w = ldpk(xc + p * P);
+                    },
+                    [&](int, const Pk<V>& u, const Pk<V>& w) { pk_msub(acc, u, w); });
                 const V xij = (METHOD == 0) ? scal(acc, si) : acc;
                 Xm[j * LD + i] = xij;
                 Xm[i * LD + j] = cj(xij);
@@ -205,12 +236,13 @@ CI_D void wpm_matrix(const V* __restrict__ ab, V* xb, int n, bool valid, int64_t
                 // now hold conj(x_ik), rows <= i are zero
                 V d = mk<V>(si);
                 const V* xc = Xm + i * LD;
-                const int p0 = (i + 1) / P;
-                for (int p = p0; p < np / P; ++p) {
-                    const Pk<V> w = ldpk(xc + p * P);
-#pragma unroll
-                    for (int c = 0; c < P; ++c) msub(d, Wm[(p * P + c) * LD + i], w.v[c]);
-                }
+                pk_loop<V>(
+                    p0, np / P,
+                    [&](int p, Pk<V>& u, Pk<V>& w) {
+                        u = ldpk(ri + p * P);
+                        w = ldpk(xc + p * P);
+                    },
+                    [&](int, const Pk<V>& u, const Pk<V>& w) { pk_msub(d, u, w); });
                 Xm[i * LD + i] = realpart_only((METHOD == 0) ? scal(d, si) : d);
             }
             __syncthreads();
@@ -225,12 +257,16 @@ CI_D void wpm_matrix(const V* __restrict__ ab, V* xb, int n, bool valid, int64_t
                     W e = widen(mk<V>(R(k == j ? 1 : 0)));
                     const V* ak = Am + k * LD;
                     const V* xc = Xm + j * LD;
-                    for (int p = 0; p < np / P; ++p) {
-                        const Pk<V> u = ldpk(ak + p * P);
-                        const Pk<V> w = ldpk(xc + p * P);
+                    pk_loop<V>(
+                        0, np / P,
+                        [&](int p, Pk<V>& u, Pk<V>& w) {
+                            u = ldpk(ak + p * P);
+                            w = ldpk(xc + p * P);
+                        },
+                        [&](int, const Pk<V>& u, const Pk<V>& w) {
 #pragma unroll
-                        for (int c = 0; c < P; ++c) msubc(e, widen(u.v[c]), widen(w.v[c]));
-                    }
+                            for (int c = 0; c < P; ++c) msubc(e, widen(u.v[c]), widen(w.v[c]));
+                        });
                     Wm[j * LD + k] = narrow<V>(e);
                 }
                 __syncthreads();
@@ -240,12 +276,16 @@ CI_D void wpm_matrix(const V* __restrict__ ab, V* xb, int n, bool valid, int64_t
                     V acc = Xm[j * LD + i];
                     const V* xi = Xm + i * LD;
                     const V* ec = Wm + j * LD;
-                    for (int p = 0; p < np / P; ++p) {
-                        const Pk<V> u = ldpk(xi + p * P);
-                        const Pk<V> w = ldpk(ec + p * P);
+                    pk_loop<V>(
+                        0, np / P,
+                        [&](int p, Pk<V>& u, Pk<V>& w) {
+                            u = ldpk(xi + p * P);
+                            w = ldpk(ec + p * P);
+                        },
+                        [&](int, const Pk<V>& u, const Pk<V>& w) {
 #pragma unroll
-                        for (int c = 0; c < P; ++c) madd(acc, cj(u.v[c]), w.v[c]);
-                    }
+                            for (int c = 0; c < P; ++c) madd(acc, cj(u.v[c]), w.v[c]);
+                        });
                     if (i == j) acc = realpart_only(acc);
                     if (valid && j < n && i < n && i <= j) {
                         const V v = fail ? nan_value<V>() : acc;
