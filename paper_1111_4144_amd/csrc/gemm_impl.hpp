@@ -48,6 +48,10 @@ struct GemmArgs {
     int splits = 1;
     int kc = 0;
     int64_t cstride = 0;
+    // triangular operands: bit 0 = op(A) is zero left of the diagonal (row i
+    // has no k < i), bit 1 = op(B) is zero above it (column j has no k < j);
+    // each output tile then starts its K range at its first row / column
+    int tri = 0;
 };
 
 constexpr int GT_M = 128, GT_N = 128;
@@ -178,8 +182,11 @@ k_gemm(GemmArgs p)
     int bm, bn, split;
     gemm_tile(blockIdx.x, gridDim.x, ntiles, tiles_n, p.uplo, bm, bn, split);
     const int m0 = bm * GT_M, n0 = bn * GT_N;
-    const int kb = split * p.kc;
-    const int K = min(p.K - kb, p.kc);
+    int kb = split * p.kc;
+    const int ke = min(p.K, kb + p.kc);
+    if (p.tri & 1) kb = max(kb, m0);
+    if (p.tri & 2) kb = max(kb, n0);
+    const int K = max(0, ke - kb);
     const TA* Ap = static_cast<const TA*>(p.A) + (p.transA ? (int64_t)kb * p.lda : kb);
     const TB* Bp = static_cast<const TB*>(p.B) + (p.transB ? kb : (int64_t)kb * p.ldb);
 

@@ -20,6 +20,8 @@
 // X <- X + X (I - A X) with the residual I - A X as an FP64 MFMA GEMM on the
 // exact FP32 inputs and the update as an FP32 GEMM.
 #include <algorithm>
+#include <cstdlib>
+#include <cstring>
 
 #include "ci_large.hpp"
 #include "ci_launch.hpp"
@@ -103,6 +105,9 @@ k_lg_diag_factor(T* __restrict__ W, int64_t ldw, int r0, int nl, const double* _
     // FP64 sum of squares of column j of R above the diagonal, accumulated as
     // its entries are produced (the pivot of step j is dacc_j minus it)
     double sq = 0.0;
+    // this column's FP64 pivot accumulator, read once (a global load inside
+    // the serial loop would put its latency on every step)
+    const double dj = (MIXED && j < nl) ? dacc[r0 + j] : 1.0;
     for (int i = 0; i < NB; ++i) {
         const T* ci = Rm + i * LD;
         const T* cj = Rm + j * LD;
@@ -114,7 +119,7 @@ k_lg_diag_factor(T* __restrict__ W, int64_t ldw, int r0, int nl, const double* _
         const T acc = cj[i] - dot;
         __syncthreads();
         if (j == i) {
-            const double piv = MIXED ? ((i < nl ? dacc[r0 + i] : 1.0) - sq) : (double)acc;
+            const double piv = MIXED ? (dj - sq) : (double)acc;
             const bool ok = piv > 0.0 && piv < __builtin_inf();
             const double r = sqrt(piv);
             Rm[i * LD + i] = (T)r;
@@ -201,13 +206,18 @@ k_lg_diag_inverse(const T* __restrict__ W, int64_t ldw, int r0, int nl,
     sv[j] = T(1) / Rm[j * LD + j];
     __syncthreads();
     const int pend = (nl + P - 1) / P;
+    // w_ij of this column, fetched one step ahead so that no global load
+    // latency sits inside the serial loop
+    T w_next = (has_w && j < nl && nl > 0) ? wblk[(int64_t)(nl - 1) * NB + j] : T(0);
     for (int i = nl - 1; i >= 0; --i) {
         const T si = sv[i];
+        const T w_cur = w_next;
+        if (has_w && j < nl && i > 0) w_next = wblk[(int64_t)(i - 1) * NB + j];
         if (j > i && j < nl) {
             const T dot = lg_dot<T>((i + 1) / P, pend,
                                     [&](int p, T (&v)[P]) { lg_ldv(Rm + i * LD + p * P, v); },
                                     [&](int p, T (&v)[P]) { lg_ldv(Xm + j * LD + p * P, v); });
-            const T xij = si * ((has_w ? -wblk[(int64_t)i * NB + j] : T(0)) - dot);
+            const T xij = si * (-w_cur - dot);
             Xm[j * LD + i] = xij;
             Xm[i * LD + j] = xij;
         }
@@ -216,7 +226,7 @@ k_lg_diag_inverse(const T* __restrict__ W, int64_t ldw, int r0, int nl,
             const T dot = lg_dot<T>((i + 1) / P, pend,
                                     [&](int p, T (&v)[P]) { lg_ldv(Rm + i * LD + p * P, v); },
                                     [&](int p, T (&v)[P]) { lg_ldv(Xm + i * LD + p * P, v); });
-            Xm[i * LD + i] = si * (si - (has_w ? wblk[(int64_t)i * NB + i] : T(0)) - dot);
+            Xm[i * LD + i] = si * (si - w_cur - dot);
         }
         __syncthreads();
     }
@@ -279,6 +289,7 @@ __global__ void k_lg_symmetrize(const TS* __restrict__ src, int64_t lds, TD* __r
     }
 }
 
+// upper_only: 0 whole matrix, 1 upper triangle, 2 upper triangle and zeros below
 template <class TS, class TD>
 __global__ void k_lg_copy(const TS* __restrict__ src, int64_t lds, TD* __restrict__ dst, int64_t ldd,
                           int rows, int cols, int upper_only)
@@ -286,7 +297,10 @@ __global__ void k_lg_copy(const TS* __restrict__ src, int64_t lds, TD* __restric
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (int64_t)rows * cols) return;
     const int i = (int)(e / cols), jj = (int)(e % cols);
-    if (upper_only && jj < i) return;
+    if (upper_only && jj < i) {
+        if (upper_only == 2) dst[(int64_t)i * ldd + jj] = TD(0);
+        return;
+    }
     dst[(int64_t)i * ldd + jj] = (TD)src[(int64_t)i * lds + jj];
 }
 
@@ -338,9 +352,10 @@ struct LgWork {
 template <class T, class TA, class TB>
 static hipError_t gemm(int M, int N, int K, double alpha, const TA* A, int64_t lda, int ta,
                        const TB* B, int64_t ldb, int tb, double beta, T* C, int64_t ldc, int uplo,
-                       hipStream_t s)
+                       hipStream_t s, int tri = 0)
 {
     GemmArgs g{M, N, K, alpha, beta, A, lda, ta, B, ldb, tb, C, ldc, uplo};
+    g.tri = tri;
     return gemm_launch<T, TA, TB>(g, s);
 }
 
@@ -350,13 +365,14 @@ static hipError_t gemm(int M, int N, int K, double alpha, const TA* A, int64_t l
 template <class T>
 static hipError_t gemm_splitk(int M, int N, int K, double alpha, const T* A, int64_t lda, int ta,
                               const T* B, int64_t ldb, int tb, T* C, int64_t ldc, T* part,
-                              int64_t cap, hipStream_t s)
+                              int64_t cap, hipStream_t s, int tri = 0)
 {
     const int tiles = ((M + GT_M - 1) / GT_M) * ((N + GT_N - 1) / GT_N);
     int splits = (512 + tiles - 1) / tiles;
     splits = std::min<int64_t>(splits, std::max(1, K / 64));
     splits = (int)std::min<int64_t>(splits, cap / ((int64_t)M * N));
-    if (splits <= 1) return gemm<T, T, T>(M, N, K, alpha, A, lda, ta, B, ldb, tb, 0.0, C, ldc, 0, s);
+    if (splits <= 1)
+        return gemm<T, T, T>(M, N, K, alpha, A, lda, ta, B, ldb, tb, 0.0, C, ldc, 0, s, tri);
     constexpr int BK = G_BK<T>;
     const int kc = ((K + splits - 1) / splits + BK - 1) / BK * BK;   // whole stages
     splits = (K + kc - 1) / kc;            // every split has kc > 0 terms
@@ -365,6 +381,7 @@ static hipError_t gemm_splitk(int M, int N, int K, double alpha, const T* A, int
     g.splits = splits;
     g.kc = kc;
     g.cstride = pstride;
+    g.tri = tri;
     hipError_t e = gemm_launch<T, T, T>(g, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_lg_reduce<T>, dim3(blocks_for((int64_t)M * N)), dim3(256), 0, s, part,
@@ -449,6 +466,68 @@ static hipError_t lg_inverse_from_r(const T* W, int64_t n, const T* rinv, T* X, 
     return hipGetLastError();
 }
 
+// diagonal block of M = R^{-1}: the upper triangle from the panel inverse,
+// zeros below (the triangular GEMMs read whole diagonal tiles)
+template <class T>
+__global__ void k_lg_put_diag(const T* __restrict__ rv, T* __restrict__ W, int64_t ldw, int jb)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr int NB = LG_NB<T>;
+    if (e >= jb * jb) return;
+    const int i = e / jb, jj = e % jb;
+    W[(int64_t)i * ldw + jj] = (jj >= i) ? rv[(int64_t)i * NB + jj] : T(0);
+}
+
+// M = R^{-1} in place over R in W (blocked triangular inverse, block columns
+// left to right; the zero blocks below the diagonal are never touched):
+//   M_{<J,J} = -(M_{<J,<J} R_{<J,J}) M_JJ,   M_JJ = R_JJ^{-1} (from the factor)
+template <class T>
+static hipError_t lg_trtri(T* W, int64_t n, const T* rinv, T* ctmp, T* part, int64_t cap,
+                           hipStream_t s)
+{
+    constexpr int NB = LG_NB<T>;
+    for (int64_t j0 = 0; j0 < n; j0 += NB) {
+        const int jb = (int)std::min<int64_t>(NB, n - j0);
+        const T* rv = rinv + (j0 / NB) * NB * NB;
+        if (j0 > 0) {
+            // ctmp (j0 x jb) = M_{<J,<J} R_{<J,J}; M is upper triangular by tiles
+            hipError_t e = gemm_splitk<T>((int)j0, jb, (int)j0, 1.0, W, n, 0, W + j0, n, 0, ctmp,
+                                          jb, part, cap, s, /*tri=*/1);
+            if (e != hipSuccess) return e;
+            e = gemm<T, T, T>((int)j0, jb, jb, -1.0, ctmp, jb, 0, rv, NB, 0, 0.0, W + j0, n, 0, s);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(k_lg_put_diag<T>, dim3(blocks_for((int64_t)jb * jb)), dim3(256), 0, s, rv,
+                           W + j0 * n + j0, n, jb);
+    }
+    return hipGetLastError();
+}
+
+// X = M M^T (upper half, then mirrored): x_ij = sum_{k >= j} m_ik m_jk, one
+// launch over the upper tiles, each starting its K range at its first column
+template <class T>
+static hipError_t lg_lauum(const T* W, int64_t n, T* X, int64_t ldx, hipStream_t s)
+{
+    hipError_t e = gemm<T, T, T>((int)n, (int)n, (int)n, 1.0, W, n, 0, W, n, 1, 0.0, X, ldx, 1, s,
+                                 /*tri=*/2);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_lg_symmetrize<T, T>), dim3((unsigned)((n + 31) / 32), (unsigned)((n + 31) / 32)),
+                       dim3(32, 8), 0, s, X, ldx, X, ldx, (int)n);
+    return hipGetLastError();
+}
+
+// Inverse from the factor: TRTRI + M M^T (default), or the Section IV
+// recurrence in block form (environment CHOLINV_LARGE_INVERSE=blocked_iv).
+static int lg_use_blocked_iv()
+{
+    static int v = -1;
+    if (v < 0) {
+        const char* e = std::getenv("CHOLINV_LARGE_INVERSE");
+        v = (e && std::strcmp(e, "blocked_iv") == 0) ? 1 : 0;
+    }
+    return v;
+}
+
 template <class T, int MIXED>
 static hipError_t lg_inverse(int64_t n, const T* a, int64_t lda, T* x, int64_t ldx, int ns_steps,
                              int32_t* info, void* work, hipStream_t s)
@@ -465,14 +544,20 @@ static hipError_t lg_inverse(int64_t n, const T* a, int64_t lda, T* x, int64_t l
         hipError_t e0 = fill_i32(info, 1, 0, s);
         if (e0 != hipSuccess) return e0;
     }
+    // upper triangle of A; zeros below (the triangular products read whole tiles)
     hipLaunchKernelGGL((k_lg_copy<T, T>), dim3(blocks_for(n * n)), dim3(256), 0, s, a, lda, W, n,
-                       (int)n, (int)n, 1);
+                       (int)n, (int)n, 2);
     if (MIXED)
         hipLaunchKernelGGL(k_lg_dacc_init<T>, dim3(blocks_for(n)), dim3(256), 0, s, a, lda, (int)n,
                            dacc);
     hipError_t e = lg_factor<T, MIXED>(W, n, dacc, rinv, info, s);
     if (e != hipSuccess) return e;
-    e = lg_inverse_from_r<T>(W, n, rinv, x, ldx, ctmp, wblk, part, L.part_elems, s);
+    if (lg_use_blocked_iv()) {
+        e = lg_inverse_from_r<T>(W, n, rinv, x, ldx, ctmp, wblk, part, L.part_elems, s);
+    } else {
+        e = lg_trtri<T>(W, n, rinv, ctmp, part, L.part_elems, s);
+        if (e == hipSuccess) e = lg_lauum<T>(W, n, x, ldx, s);
+    }
     if (e != hipSuccess) return e;
     if (MIXED && ns_steps > 0) {
         double* E = reinterpret_cast<double*>(w + L.emat);

@@ -140,3 +140,33 @@ def test_large_mixed_refinement_improves():
     x1, _ = _inverse(a, "f32", "mixed", ns_steps=1)
     e0, e1 = float(rel_err(x0, ref)), float(rel_err(x1, ref))
     assert e1 < 0.5 * e0, (e0, e1)
+
+
+def test_blocked_section_iv_variant():
+    """The Section IV recurrence in block form (selected by the environment in
+    a child process) against the oracle, next to the default inverse."""
+    import os
+    import subprocess
+    import sys
+    torch_cuda()
+    code = r'''
+import numpy as np, torch
+import oracle as O
+from paper_1111_4144_amd import api, inputs as I
+from tests.helpers import rel_err
+worst = 0.0
+for n, dt, prec in [(200, np.float64, "plain"), (333, np.float32, "plain"), (333, np.float32, "mixed")]:
+    a = I.large_spd(n, seed=77 + n, top=1e3)
+    ref, _ = O.inv_prop(a.astype(dt).astype(np.float64))
+    x = api.inverse(torch.from_numpy(a.astype(dt)).cuda(), precision=prec).cpu().numpy()
+    tol = 1e-12 if dt == np.float64 else 2e-6
+    err = float(rel_err(x.astype(np.float64), ref))
+    assert err <= tol * 1e3, (n, prec, err)
+print("blocked_iv ok")
+'''
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, CHOLINV_LARGE_INVERSE="blocked_iv", PYTHONPATH=root)
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True,
+                       text=True, timeout=240)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
+    assert "blocked_iv ok" in r.stdout
