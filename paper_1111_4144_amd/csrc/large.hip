@@ -82,8 +82,22 @@ __device__ __forceinline__ void lg_ldv(const T* q, T (&v)[LG_P<T>])
 }
 
 // ---- diagonal block: Cholesky (Crout, FP64 pivots when mixed) + R^{-1} --------
+// LG_TPC adjacent lanes share column j: lane h of the column takes the
+// packets p = h, h + LG_TPC, ... of every inner product, and the partial sums
+// are combined with lane shuffles, so the serial steps are spread over
+// LG_TPC times more waves.
+constexpr int LG_TPC = 4;
+
+template <class T>
+__device__ __forceinline__ T lg_colsum(T v)
+{
+#pragma unroll
+    for (int o = 1; o < LG_TPC; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
 template <class T, int MIXED>
-__global__ void __launch_bounds__(LG_NB<T>)
+__global__ void __launch_bounds__(LG_NB<T> * LG_TPC)
 k_lg_diag_factor(T* __restrict__ W, int64_t ldw, int r0, int nl, const double* __restrict__ dacc,
                  T* __restrict__ rinv, int32_t* __restrict__ info)
 {
@@ -92,9 +106,9 @@ k_lg_diag_factor(T* __restrict__ W, int64_t ldw, int r0, int nl, const double* _
     T* Rm = reinterpret_cast<T*>(smem_raw);
     T* Ym = Rm + NB * LD;
     T* sv = Ym + NB * LD;                          // 1/r_ii, then a pivot flag
-    const int j = threadIdx.x;
+    const int j = threadIdx.x / LG_TPC, h = threadIdx.x % LG_TPC;
     T* Wb = W + (int64_t)r0 * ldw + r0;
-    for (int k = 0; k < NB; ++k) {
+    for (int k = h; k < NB; k += LG_TPC) {
         T v = (k == j) ? T(1) : T(0);
         if (j < nl && k < nl && k <= j) v = Wb[(int64_t)k * ldw + j];
         Rm[j * LD + k] = (k <= j) ? v : T(0);
@@ -111,14 +125,23 @@ k_lg_diag_factor(T* __restrict__ W, int64_t ldw, int r0, int nl, const double* _
     for (int i = 0; i < NB; ++i) {
         const T* ci = Rm + i * LD;
         const T* cj = Rm + j * LD;
-        // a_ij - sum_{k<i} r_ki r_kj: whole packets, then the partial one
+        // a_ij - sum_{k<i} r_ki r_kj: whole packets (this lane's share), then
+        // the partial one
         const int full = i / P;
-        T dot = lg_dot<T>(0, full, [&](int p, T (&v)[P]) { lg_ldv(ci + p * P, v); },
-                          [&](int p, T (&v)[P]) { lg_ldv(cj + p * P, v); });
-        for (int k = full * P; k < i; ++k) dot += ci[k] * cj[k];
+        T dot = T(0);
+        for (int p = h; p < full; p += LG_TPC) {
+            T u[P], w[P];
+            lg_ldv(ci + p * P, u);
+            lg_ldv(cj + p * P, w);
+#pragma unroll
+            for (int c = 0; c < P; ++c) dot += u[c] * w[c];
+        }
+        if (h == 0)
+            for (int k = full * P; k < i; ++k) dot += ci[k] * cj[k];
+        dot = lg_colsum(dot);
         const T acc = cj[i] - dot;
         __syncthreads();
-        if (j == i) {
+        if (j == i && h == 0) {
             const double piv = MIXED ? (dj - sq) : (double)acc;
             const bool ok = piv > 0.0 && piv < __builtin_inf();
             const double r = sqrt(piv);
@@ -130,45 +153,57 @@ k_lg_diag_factor(T* __restrict__ W, int64_t ldw, int r0, int nl, const double* _
         if (!(sv[NB] > T(0)) && !fail && i < nl) fail = i + 1;
         if (j > i) {
             const T rij = acc * sv[i];
-            Rm[j * LD + i] = rij;
+            if (h == 0) Rm[j * LD + i] = rij;
             if (MIXED) sq = fma((double)rij, (double)rij, sq);
         }
         __syncthreads();
     }
     if (j < nl)
-        for (int k = 0; k <= j; ++k) Wb[(int64_t)k * ldw + j] = Rm[j * LD + k];
+        for (int k = h; k <= j; k += LG_TPC) Wb[(int64_t)k * ldw + j] = Rm[j * LD + k];
     // Y = R^{-1}, column j: y_jj = 1/r_jj, y_ij = -(1/r_ii) sum_{k=i+1..j} r_ik y_kj.
     // Entries not computed yet are zero, and R is zero below its diagonal, so
-    // the packets may start below i+1.
-    Ym[j * LD + j] = sv[j];
+    // the packets may start below i+1.  The lanes of column j are adjacent in
+    // one wave, so lane 0's write of y_ij precedes every lane's later reads.
+    if (h == 0) Ym[j * LD + j] = sv[j];
     for (int i = NB - 2; i >= 0; --i) {
         if (i < j) {
-            // row i of R is strided in this column-major layout
-            const T acc = lg_dot<T>(
-                (i + 1) / P, j / P + 1,
-                [&](int p, T (&v)[P]) {
+            T dot = T(0);
+            for (int p = (i + 1) / P + h; p <= j / P; p += LG_TPC) {
+                T w[P];
+                lg_ldv(Ym + j * LD + p * P, w);
 #pragma unroll
-                    for (int c = 0; c < P; ++c) v[c] = Rm[(p * P + c) * LD + i];
-                },
-                [&](int p, T (&v)[P]) { lg_ldv(Ym + j * LD + p * P, v); });
-            Ym[j * LD + i] = -sv[i] * acc;
+                for (int c = 0; c < P; ++c) dot += Rm[(p * P + c) * LD + i] * w[c];
+            }
+            dot = lg_colsum(dot);
+            if (h == 0) Ym[j * LD + i] = -sv[i] * dot;
         }
     }
-    for (int i = 0; i < NB; ++i) rinv[(int64_t)i * NB + j] = (i <= j) ? Ym[j * LD + i] : T(0);
-    if (j == 0 && fail && info && info[0] == 0) info[0] = r0 + fail;
+    for (int i = h; i < NB; i += LG_TPC) rinv[(int64_t)i * NB + j] = (i <= j) ? Ym[j * LD + i] : T(0);
+    if (threadIdx.x == 0 && fail && info && info[0] == 0) info[0] = r0 + fail;
 }
 
 // ---- FP64 pivot accumulators: d_j -= sum_{k in panel} r_kj^2, j >= c0 ----------
+// 64-lane blocks over the columns; rows in batches of 8 independent loads.
 template <class T>
-__global__ void k_lg_dacc(const T* __restrict__ W, int64_t ldw, int r0, int nl, int c0, int n,
-                          double* __restrict__ dacc)
+__global__ void __launch_bounds__(64)
+k_lg_dacc(const T* __restrict__ W, int64_t ldw, int r0, int nl, int c0, int n,
+          double* __restrict__ dacc)
 {
     const int j = c0 + blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
+    const T* col = W + (int64_t)r0 * ldw + j;
     double s = dacc[j];
-    for (int k = 0; k < nl; ++k) {
-        const double v = (double)W[(int64_t)(r0 + k) * ldw + j];
-        s -= v * v;
+    int k = 0;
+    for (; k + 8 <= nl; k += 8) {
+        T v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = col[(int64_t)(k + q) * ldw];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) s = fma(-(double)v[q], (double)v[q], s);
+    }
+    for (; k < nl; ++k) {
+        const double v = (double)col[(int64_t)k * ldw];
+        s = fma(-v, v, s);
     }
     dacc[j] = s;
 }
@@ -405,7 +440,7 @@ static hipError_t lg_factor(T* W, int64_t n, double* dacc, T* rinv, int32_t* inf
         const int nl = (int)std::min<int64_t>(NB, n - r0);
         const int64_t c0 = r0 + nl, mr = n - c0;
         T* rv = rinv + (r0 / NB) * NB * NB;
-        hipLaunchKernelGGL((k_lg_diag_factor<T, MIXED>), dim3(1), dim3(NB), smem, s, W, n, (int)r0,
+        hipLaunchKernelGGL((k_lg_diag_factor<T, MIXED>), dim3(1), dim3(NB * LG_TPC), smem, s, W, n, (int)r0,
                            nl, dacc, rv, info);
         if (mr <= 0) break;
         // R_I,>I = R_II^{-T} A_I,>I  (in place: one M tile spans the panel)
@@ -413,7 +448,7 @@ static hipError_t lg_factor(T* W, int64_t n, double* dacc, T* rinv, int32_t* inf
                                      W + r0 * n + c0, n, 0, s);
         if (e != hipSuccess) return e;
         if (MIXED)
-            hipLaunchKernelGGL(k_lg_dacc<T>, dim3(blocks_for(mr)), dim3(256), 0, s, W, n, (int)r0,
+            hipLaunchKernelGGL(k_lg_dacc<T>, dim3(blocks_for(mr, 64)), dim3(64), 0, s, W, n, (int)r0,
                                nl, (int)c0, (int)n, dacc);
         // A_>I,>I -= R_I,>I^T R_I,>I  (upper half)
         e = gemm<T, T, T>((int)mr, (int)mr, nl, -1.0, W + r0 * n + c0, n, 1, W + r0 * n + c0, n, 0,

@@ -8,11 +8,12 @@
 //   3. scatter every matrix index into the sorted list.
 // Tiles: an order n <= 8 tile is up to 64 matrices (one lane each, registers);
 // 9..16 up to 4 matrices (16-lane groups padded to 16 with the identity,
-// which leaves the n x n block exact); 17..32 up to 2 and 33..64 one matrix
-// (LDS-resident, one lane per column).  The persistent kernel's waves take
-// tiles from an atomic counter until none are left (every wave reaches that
-// exit), so the largest, slowest tiles start first and the small ones fill in.
-// Results do not depend on which wave takes which tile.
+// which leaves the n x n block exact); 17..32 up to 2 (LDS-resident, one lane
+// per column) and 33..64 one matrix (LDS-resident, four lanes per column,
+// four waves).  Two persistent kernels, one per block shape, take tiles from
+// their own atomic counters until none are left (every wave reaches that
+// exit): first orders 33..64, then the rest, largest orders first within
+// each.  Results do not depend on which wave takes which tile.
 #pragma once
 
 #include "group_impl.hpp"
@@ -22,8 +23,10 @@
 namespace ci {
 
 struct VarlenPlan {
-    int next;              // tile counter of the persistent kernel
+    int next;              // tile counter of the orders <= 32 kernel (starts at nbig)
     int ntiles;
+    int next_big;          // tile counter of the orders 33..64 kernel (starts at 0)
+    int nbig;              // tiles of orders 33..64 (one matrix each, first in the order)
     int count[65];         // matrices per order
     int item_start[65];    // first position of order n in the sorted list
     int tile_start[65];    // tile range of order n: [tile_start, tile_end)
@@ -68,7 +71,9 @@ __global__ void k_vl_scan(VarlenPlan* plan)
         items += c;
     }
     plan->ntiles = tiles;
-    plan->next = 0;
+    plan->nbig = plan->tile_end[33];
+    plan->next = plan->nbig;
+    plan->next_big = 0;
 }
 
 __global__ void k_vl_scatter(const int32_t* __restrict__ ns, int64_t batch, int nmax,
@@ -142,7 +147,7 @@ k_varlen(const V* __restrict__ a, V* x, const int64_t* __restrict__ offs,
                                                            ns_steps, lane % 16,
                                                            (valid && info) ? info + b : nullptr,
                                                            nullptr);
-        } else if (n <= 32) {
+        } else {
             const int g = lane / 32;
             const bool valid = g < cnt;
             const int b = sorted[first + (valid ? g : 0)];
@@ -150,13 +155,36 @@ k_varlen(const V* __restrict__ a, V* x, const int64_t* __restrict__ offs,
             wpm_matrix<V, 32, OP_INV, METHOD, MIXED>(
                 a + o, x + o, n, valid, n, n, ns_steps, fill, (valid && info) ? info + b : nullptr,
                 nullptr, smem_raw + (size_t)g * wpm_smem_per_matrix<V, 32, MIXED>(), lane % 32);
-        } else {
-            const int b = sorted[first];
-            const int64_t o = offs[b];
-            wpm_matrix<V, 64, OP_INV, METHOD, MIXED>(a + o, x + o, n, true, n, n, ns_steps, fill,
-                                                     info ? info + b : nullptr, nullptr, smem_raw,
-                                                     lane);
         }
+        __syncthreads();
+    }
+}
+
+// Orders 33..64: one matrix per 256-lane block, four lanes per column.
+constexpr int VL_BIG_TPC = 4;
+
+template <class V, int METHOD, int MIXED>
+__global__ void __launch_bounds__(64 * VL_BIG_TPC)
+k_varlen_big(const V* __restrict__ a, V* x, const int64_t* __restrict__ offs,
+             const int32_t* __restrict__ sorted, VarlenPlan* plan, int ns_steps, int fill,
+             int32_t* __restrict__ info)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int s_tile;
+    const int j = threadIdx.x / VL_BIG_TPC, h = threadIdx.x % VL_BIG_TPC;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(&plan->next_big, 1);
+        __syncthreads();
+        const int t = s_tile;
+        __syncthreads();
+        if (t >= plan->nbig) break;
+        int n = 64;
+        while (n > 33 && t >= plan->tile_end[n]) --n;
+        const int b = sorted[plan->item_start[n] + (t - plan->tile_start[n])];
+        const int64_t o = offs[b];
+        wpm_matrix<V, 64, OP_INV, METHOD, MIXED, VL_BIG_TPC>(a + o, x + o, n, true, n, n, ns_steps,
+                                                             fill, info ? info + b : nullptr,
+                                                             nullptr, smem_raw, j, h);
         __syncthreads();
     }
 }
@@ -178,24 +206,37 @@ static hipError_t varlen_run(int64_t batch, const int32_t* n_dev, const int64_t*
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
 
+    auto kbig = k_varlen_big<V, METHOD, MIXED>;
     auto kern = k_varlen<V, METHOD, MIXED>;
     constexpr size_t s64 = wpm_smem_per_matrix<V, 64, MIXED>();
     constexpr size_t s32 = 2 * wpm_smem_per_matrix<V, 32, MIXED>();
-    const size_t smem = n_max > 32 ? s64 : (n_max > 16 ? s32 : 0);
     static bool attr = false;
     if (!attr) {
+        e = hipFuncSetAttribute((const void*)kbig, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)s64);
+        if (e != hipSuccess) return e;
         e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)(s64 > s32 ? s64 : s32));
+                                (int)s32);
         if (e != hipSuccess) return e;
         attr = true;
     }
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, 64, smem) !=
-            hipSuccess || per_cu < 1)
-        per_cu = 1;
-    const int64_t grid = (int64_t)device_cus() * per_cu;
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64), smem, s, (const V*)a, (V*)x, off_dev,
-                       sorted, plan, ns_steps, fill, info);
+    auto grid_of = [](const void* k, int threads, size_t smem) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, threads, smem) !=
+                hipSuccess || per_cu < 1)
+            per_cu = 1;
+        return (int64_t)device_cus() * per_cu;
+    };
+    if (n_max > 32) {
+        hipLaunchKernelGGL(kbig, dim3((unsigned)grid_of((const void*)kbig, 64 * VL_BIG_TPC, s64)),
+                           dim3(64 * VL_BIG_TPC), s64, s, (const V*)a, (V*)x, off_dev, sorted, plan,
+                           ns_steps, fill, info);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const size_t smem = n_max > 16 ? s32 : 0;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid_of((const void*)kern, 64, smem)), dim3(64), smem, s,
+                       (const V*)a, (V*)x, off_dev, sorted, plan, ns_steps, fill, info);
     return hipGetLastError();
 }
 

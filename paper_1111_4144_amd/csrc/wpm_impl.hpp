@@ -48,26 +48,42 @@ CI_D Pk<V> ldpk(const V* p)
     return r;
 }
 
-// Loop over packets [p0, p1): fetch(p, u, w) loads the two operand packets,
+// Loop over packets p0, p0 + STRIDE, ... below p1: fetch(p, u, w) loads the two operand packets,
 // body(p, u, w) consumes them.  Four packets are fetched before their bodies
 // run, so several LDS loads are in flight at once.
-template <class V, class F, class B>
+template <class V, int STRIDE = 1, class F, class B>
 CI_D void pk_loop(int p0, int p1, F fetch, B body)
 {
     int p = p0;
-    for (; p + 4 <= p1; p += 4) {
+    for (; p + 3 * STRIDE < p1; p += 4 * STRIDE) {
         Pk<V> u[4], w[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) fetch(p + q, u[q], w[q]);
+        for (int q = 0; q < 4; ++q) fetch(p + q * STRIDE, u[q], w[q]);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) body(p + q, u[q], w[q]);
+        for (int q = 0; q < 4; ++q) body(p + q * STRIDE, u[q], w[q]);
     }
-    for (; p < p1; ++p) {
+    for (; p < p1; p += STRIDE) {
         Pk<V> u, w;
         fetch(p, u, w);
         body(p, u, w);
     }
 }
+
+// Sum over the TPC adjacent lanes that share a column.
+template <int TPC> CI_D float tpc_sum(float v)
+{
+#pragma unroll
+    for (int o = 1; o < TPC; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+template <int TPC> CI_D double tpc_sum(double v)
+{
+#pragma unroll
+    for (int o = 1; o < TPC; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+template <int TPC> CI_D cf tpc_sum(cf v) { return cf{tpc_sum<TPC>(v.re), tpc_sum<TPC>(v.im)}; }
+template <int TPC> CI_D cd tpc_sum(cd v) { return cd{tpc_sum<TPC>(v.re), tpc_sum<TPC>(v.im)}; }
 
 // acc -= sum over the packet of conj(a) * b   (P-length partial dot)
 template <class V>
@@ -83,14 +99,17 @@ CI_D void pk_msub(V& acc, const Pk<V>& a, const Pk<V>& b)
     for (int c = 0; c < WPM_P<V>; ++c) msub(acc, a.v[c], b.v[c]);
 }
 
-// One matrix per group of NB lanes; `base` is the group's LDS area
-// (wpm_smem_per_matrix bytes), j the lane's column.  Every lane of the block
-// must call this together (it synchronises the block); `valid` only gates
-// global memory accesses.
-template <class V, int NB, int OP, int METHOD, int MIXED>
+// One matrix per group of NB * TPC lanes; `lds` is the group's LDS area
+// (wpm_smem_per_matrix bytes), j the lane's column and h its index among the
+// TPC adjacent lanes of that column: lane h takes packets h, h + TPC, ... of
+// every inner product (combined by lane shuffles), and every TPC-th row of
+// the loads, stores and refinement loops.  Every lane of the block must call
+// this together (it synchronises the block); `valid` only gates global
+// memory accesses.
+template <class V, int NB, int OP, int METHOD, int MIXED, int TPC = 1>
 CI_D void wpm_matrix(const V* __restrict__ ab, V* xb, int n, bool valid, int64_t lda, int64_t ldx,
                      int ns_steps, int fill, int32_t* info_b, typename vt<V>::real* dout_b,
-                     unsigned char* lds, int j)
+                     unsigned char* lds, int j, int h = 0)
 {
     using R = typename vt<V>::real;
     using W = typename vt<V>::wide;
@@ -107,7 +126,7 @@ CI_D void wpm_matrix(const V* __restrict__ ab, V* xb, int n, bool valid, int64_t
 
     // ---- load: column j of the Hermitian A (only the upper triangle is read),
     // identity beyond n; W and X start at zero
-    for (int k = 0; k < NB; ++k) {
+    for (int k = h; k < NB; k += TPC) {
         V v = mk<V>(R(k == j ? 1 : 0));
         if (valid && j < n && k < n) {
             v = (k <= j) ? ab[k * lda + j] : cj(ab[j * lda + k]);
@@ -130,34 +149,37 @@ CI_D void wpm_matrix(const V* __restrict__ ab, V* xb, int n, bool valid, int64_t
     for (int i = 0; i < np; ++i) {
         const V* ci_ = Wm + i * LD;     // column i
         const V* cj_ = Wm + j * LD;     // column j
-        V acc = cj_[i];                 // a_ij (j >= i)
+        V part = zero;                  // this lane's share of the sum
         const int full = i / P;
-        pk_loop<V>(
-            0, full,
+        pk_loop<V, TPC>(
+            h, full,
             [&](int p, Pk<V>& u, Pk<V>& w) {
                 u = ldpk(ci_ + p * P);
                 w = ldpk(cj_ + p * P);
             },
             [&](int p, const Pk<V>& u, const Pk<V>& w) {
                 if constexpr (METHOD == 0) {
-                    pk_msubc(acc, u, w);
+                    pk_msubc(part, u, w);
                 } else {
                     // LDL: sum conj(r_ki) d_k r_kj with d_k in sv[NB + k]
 #pragma unroll
                     for (int c = 0; c < P; ++c)
-                        msubc(acc, scal(u.v[c], sv[NB + p * P + c]), w.v[c]);
+                        msubc(part, scal(u.v[c], sv[NB + p * P + c]), w.v[c]);
                 }
             });
-        for (int k = full * P; k < i; ++k) {
-            const V u = ci_[k];
-            if constexpr (METHOD == 0) msubc(acc, u, cj_[k]);
-            else msubc(acc, scal(u, sv[NB + k]), cj_[k]);
+        if (h == 0) {
+            for (int k = full * P; k < i; ++k) {
+                const V u = ci_[k];
+                if constexpr (METHOD == 0) msubc(part, u, cj_[k]);
+                else msubc(part, scal(u, sv[NB + k]), cj_[k]);
+            }
         }
+        const V acc = add(cj_[i], tpc_sum<TPC>(part));   // a_ij - sum (j >= i)
         const double pd = (double)re(cj_[i]) - sq;   // meaningful on lane i only
         // lane i owns the pivot: FP64 when mixed, else the compute precision
         const R prc = MIXED ? (R)pd : re(acc);
         __syncthreads();                       // every lane has read row i inputs
-        if (j == i) {
+        if (j == i && h == 0) {
             bool ok;
             R sinv, rdiag;
             if constexpr (METHOD == 0) {
@@ -186,7 +208,7 @@ CI_D void wpm_matrix(const V* __restrict__ ab, V* xb, int n, bool valid, int64_t
         if (!(sv[2 * NB] > R(0)) && !fail) fail = i + 1;
         if (j > i) {
             const V rij = scal(acc, sv[i]);
-            Wm[j * LD + i] = rij;
+            if (h == 0) Wm[j * LD + i] = rij;
             if constexpr (MIXED) {
                 if constexpr (METHOD == 0) sq += abs2_d(rij);
                 else sq = fma((double)sv[NB + i], abs2_d(rij), sq);
@@ -198,10 +220,10 @@ CI_D void wpm_matrix(const V* __restrict__ ab, V* xb, int n, bool valid, int64_t
     if constexpr (OP == OP_CHOL_FACTOR || OP == OP_LDL_FACTOR) {
         constexpr int J0 = (OP == OP_LDL_FACTOR) ? 1 : 0;
         if (valid && j < n) {
-            for (int k = 0; k + J0 <= j; ++k) xb[k * ldx + j] = Wm[j * LD + k];
-            if constexpr (OP == OP_LDL_FACTOR) dout_b[j] = sv[NB + j];
+            for (int k = h; k + J0 <= j; k += TPC) xb[k * ldx + j] = Wm[j * LD + k];
+            if constexpr (OP == OP_LDL_FACTOR) if (h == 0) dout_b[j] = sv[NB + j];
         }
-        if (valid && j == 0 && info_b) *info_b = fail;
+        if (valid && j == 0 && h == 0 && info_b) *info_b = fail;
         return;
     } else {
         // ---- Section IV back-substitution, rows i = np-1 .. 0 ----------------
@@ -209,7 +231,7 @@ CI_D void wpm_matrix(const V* __restrict__ ab, V* xb, int n, bool valid, int64_t
         // (W[i][k] = r_ik for k > i), so both operands below are contiguous
         // packets.  Entries k <= i of that column still hold R's column i, but
         // they meet rows <= i of X, which are zero until row i is produced.
-        for (int k = 0; k < j; ++k) Wm[k * LD + j] = Wm[j * LD + k];
+        for (int k = h; k < j; k += TPC) Wm[k * LD + j] = Wm[j * LD + k];
         __syncthreads();
         for (int i = np - 1; i >= 0; --i) {
             const R si = sv[i];
@@ -219,31 +241,35 @@ CI_D void wpm_matrix(const V* __restrict__ ab, V* xb, int n, bool valid, int64_t
                 // x_ij = -s_i sum_{k>i} r_ik xh_kj  (LDL: without s_i)
                 V acc = zero;
                 const V* xc = Xm + j * LD;
-                pk_loop<V>(
-                    p0, np / P,
+                pk_loop<V, TPC>(
+                    p0 + h, np / P,
                     [&](int p, Pk<V>& u, Pk<V>& w) {
                         u = ldpk(ri + p * P);
                         w = ldpk(xc + p * P);
                     },
                     [&](int, const Pk<V>& u, const Pk<V>& w) { pk_msub(acc, u, w); });
+                acc = tpc_sum<TPC>(acc);
                 const V xij = (METHOD == 0) ? scal(acc, si) : acc;
-                Xm[j * LD + i] = xij;
-                Xm[i * LD + j] = cj(xij);
+                if (h == 0) {
+                    Xm[j * LD + i] = xij;
+                    Xm[i * LD + j] = cj(xij);
+                }
             }
             __syncthreads();
             if (j == i) {
                 // x_ii = s_i (s_i - sum_{k>i} r_ik conj(x_ik)); X column i rows > i
                 // now hold conj(x_ik), rows <= i are zero
-                V d = mk<V>(si);
+                V d = zero;
                 const V* xc = Xm + i * LD;
-                pk_loop<V>(
-                    p0, np / P,
+                pk_loop<V, TPC>(
+                    p0 + h, np / P,
                     [&](int p, Pk<V>& u, Pk<V>& w) {
                         u = ldpk(ri + p * P);
                         w = ldpk(xc + p * P);
                     },
                     [&](int, const Pk<V>& u, const Pk<V>& w) { pk_msub(d, u, w); });
-                Xm[i * LD + i] = realpart_only((METHOD == 0) ? scal(d, si) : d);
+                d = add(mk<V>(si), tpc_sum<TPC>(d));
+                if (h == 0) Xm[i * LD + i] = realpart_only((METHOD == 0) ? scal(d, si) : d);
             }
             __syncthreads();
         }
@@ -252,7 +278,7 @@ CI_D void wpm_matrix(const V* __restrict__ ab, V* xb, int n, bool valid, int64_t
         // X1 = X + X E, written straight to the output; later steps reload X.
         if (MIXED && ns_steps > 0) {
             for (int step = 0; step < ns_steps; ++step) {
-                for (int k = 0; k < np; ++k) {
+                for (int k = h; k < np; k += TPC) {
                     // e_kj = delta_kj - sum_m a_km x_mj = delta - sum_m conj(a_mk) x_mj
                     W e = widen(mk<V>(R(k == j ? 1 : 0)));
                     const V* ak = Am + k * LD;
@@ -272,7 +298,7 @@ CI_D void wpm_matrix(const V* __restrict__ ab, V* xb, int n, bool valid, int64_t
                 __syncthreads();
                 // X1_ij = x_ij + sum_k x_ik e_kj = x_ij + sum_k conj(x_ki) e_kj; the
                 // upper half goes to the output (and is read back by a later step)
-                for (int i = 0; i < np; ++i) {
+                for (int i = h; i < np; i += TPC) {
                     V acc = Xm[j * LD + i];
                     const V* xi = Xm + i * LD;
                     const V* ec = Wm + j * LD;
@@ -297,14 +323,14 @@ CI_D void wpm_matrix(const V* __restrict__ ab, V* xb, int n, bool valid, int64_t
                     // reload the Hermitian X from the upper half just written
                     __syncthreads();
                     if (valid) {
-                        for (int k = 0; k < n; ++k)
+                        for (int k = h; k < n; k += TPC)
                             if (j < n) Xm[j * LD + k] = (k <= j) ? xb[k * ldx + j] : cj(xb[j * ldx + k]);
                     }
                     __syncthreads();
                 }
             }
         } else if (valid && j < n) {
-            for (int k = 0; k < n; ++k) {
+            for (int k = h; k < n; k += TPC) {
                 if (k <= j) {
                     const V v = fail ? nan_value<V>() : Xm[j * LD + k];
                     xb[k * ldx + j] = v;
@@ -312,28 +338,34 @@ CI_D void wpm_matrix(const V* __restrict__ ab, V* xb, int n, bool valid, int64_t
                 }
             }
         }
-        if (valid && j == 0 && info_b) *info_b = fail;
+        if (valid && j == 0 && h == 0 && info_b) *info_b = fail;
     }
 }
 
+// Lanes per column of the uniform-batch kernels: order-64 matrices spread
+// over four waves, order-32 pairs over two (more waves in flight for the same
+// LDS per matrix).
+template <int NB> constexpr int WPM_TPC = NB == 64 ? 4 : 2;
+
 template <class V, int NB, int OP, int METHOD, int MIXED>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64 * WPM_TPC<NB>)
 k_wpm(const V* __restrict__ a, V* x, int64_t batch, int n, int64_t lda, int64_t sa, int64_t ldx,
       int64_t sx, int ns_steps, int fill, int32_t* __restrict__ info,
       typename vt<V>::real* __restrict__ dout)
 {
-    constexpr int MPB = 64 / NB;                  // matrices per block (one wave)
+    constexpr int TPC = WPM_TPC<NB>;
+    constexpr int MPB = 64 / NB;                  // matrices per block
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int g = threadIdx.x / NB;
-    const int j = threadIdx.x % NB;
+    const int g = threadIdx.x / (NB * TPC);
+    const int r = threadIdx.x % (NB * TPC);
+    const int j = r / TPC, h = r % TPC;
     const int64_t b = (int64_t)blockIdx.x * MPB + g;
     const bool valid = b < batch;
     const int64_t bb = valid ? b : 0;
-    wpm_matrix<V, NB, OP, METHOD, MIXED>(a + bb * sa, x + bb * sx, n, valid, lda, ldx, ns_steps,
-                                         fill, info ? info + bb : nullptr,
-                                         dout ? dout + bb * n : nullptr,
-                                         smem_raw + (size_t)g * wpm_smem_per_matrix<V, NB, MIXED>(),
-                                         j);
+    wpm_matrix<V, NB, OP, METHOD, MIXED, TPC>(
+        a + bb * sa, x + bb * sx, n, valid, lda, ldx, ns_steps, fill, info ? info + bb : nullptr,
+        dout ? dout + bb * n : nullptr, smem_raw + (size_t)g * wpm_smem_per_matrix<V, NB, MIXED>(),
+        j, h);
 }
 
 template <class V, int NB, int OP, int METHOD, int MIXED>
@@ -354,8 +386,8 @@ static hipError_t wpm_run(const BatchArgs& p, int n, hipStream_t s)
         }
     }
     const int64_t blocks = (p.batch + MPB - 1) / MPB;
-    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64), smem, s, (const V*)p.a, (V*)p.x,
-                       p.batch, n, p.lda, p.sa, p.ldx, p.sx, p.ns_steps, p.fill, p.info,
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * WPM_TPC<NB>), smem, s, (const V*)p.a,
+                       (V*)p.x, p.batch, n, p.lda, p.sa, p.ldx, p.sx, p.ns_steps, p.fill, p.info,
                        (Rt*)p.dout);
     return hipGetLastError();
 }
