@@ -181,6 +181,36 @@ const char* chol_status_string(int code);
 /* Library version string (static storage). */
 const char* chol_version(void);
 
+/* ---- autotuner of the small-order engines --------------------------------
+ * For orders up to 16 several kernels can invert a uniform batch (engines:
+ * 1 one lane per matrix, direct loads; 2 the same with LDS staging; 3 with
+ * persistent staging; 4 sixteen-lane groups; 5 sixteen-lane groups with the
+ * Newton-Schulz step on MFMA, mixed precision only).  The choice depends on
+ * the device, so it is measured, not fixed.
+ *
+ * chol_autotune times every candidate engine of (dtype, opts) for each order
+ * n_lo..n_hi (1 <= n_lo <= n_hi <= 16) on a synthetic batch of `batch`
+ * diagonally dominant matrices on `stream`, and records the fastest (ties
+ * within 1% go to the lower engine number).  Later chol_inverse /
+ * chol_inverse_batched calls with the same dtype, precision and method use the
+ * record.  cache_path (may be NULL): a text file; entries for this device
+ * (architecture name and compute-unit count) are loaded instead of measured,
+ * and new measurements are appended.  This is a set-up call: it allocates and
+ * frees device memory (two batches and an info array) and synchronises the
+ * stream; it must not run during stream capture.  The record is process-wide
+ * and thread-safe.
+ * Returns the number of orders measured (>= 0), -k for an invalid argument k,
+ * or CI_ERR_LAUNCH - hipError_t on a HIP failure. */
+int chol_autotune(int dtype, const ci_opts* opts, int n_lo, int n_hi, int64_t batch,
+                  const char* cache_path, void* stream);
+
+/* The recorded engine for (dtype, opts precision/method, order n); 0 when
+ * the built-in choice applies.  Negative for an invalid argument. */
+int chol_tuned_engine(int dtype, const ci_opts* opts, int n);
+
+/* Forget every recorded choice. */
+void chol_autotune_clear(void);
+
 #ifdef __cplusplus
 }
 #endif

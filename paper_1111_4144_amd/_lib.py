@@ -23,7 +23,8 @@ CI_SMALL_NMAX = 64
 
 # Every symbol include/cholinv.h declares.
 EXPORTS = ("chol_factor", "ldl_factor", "chol_inverse", "chol_inverse_batched",
-           "chol_inverse_backward", "chol_workspace_size", "chol_status_string", "chol_version")
+           "chol_inverse_backward", "chol_workspace_size", "chol_status_string", "chol_version",
+           "chol_autotune", "chol_tuned_engine", "chol_autotune_clear")
 
 
 class ci_opts(ctypes.Structure):
@@ -65,6 +66,10 @@ def lib():
     L.chol_status_string.argtypes = [_i32]
     L.chol_status_string.restype = ctypes.c_char_p
     L.chol_version.restype = ctypes.c_char_p
+    L.chol_autotune.argtypes = [_i32, ctypes.POINTER(ci_opts), _i32, _i32, _i64, ctypes.c_char_p, _vp]
+    L.chol_tuned_engine.argtypes = [_i32, ctypes.POINTER(ci_opts), _i32]
+    L.chol_autotune_clear.argtypes = []
+    L.chol_autotune_clear.restype = None
     for fn in ("chol_factor", "ldl_factor", "chol_inverse", "chol_inverse_batched",
                "chol_inverse_backward"):
         getattr(L, fn).restype = _i32

@@ -11,6 +11,7 @@ on the GPU.  Calls are asynchronous on torch's current stream unless
 * ``factor(A)`` / ``ldl(A)``                    Section II / II.A factorisations
 * ``inverse_backward(X, G)``                    gA = -X Gh X
 * ``CholInverse``                               autograd.Function saving X
+* ``autotune`` / ``tuned_engine`` / ``autotune_clear``  engine choice per order
 """
 from __future__ import annotations
 
@@ -185,6 +186,47 @@ def ldl(A: torch.Tensor, *, return_info=False):
     L.check("ldl_factor", rc)
     d = d.reshape(*A.shape[:-2], n)
     return (R, d, info.reshape(A.shape[:-2])) if return_info else (R, d)
+
+
+_DT_CODE = {"f32": L.CI_F32, "f64": L.CI_F64, "c64": L.CI_C64, "c128": L.CI_C128}
+
+
+def _code_of(dtype) -> int:
+    if isinstance(dtype, str):
+        return _DT_CODE[dtype]
+    return _DT[dtype]
+
+
+def autotune(dtype, *, method="chol", precision="plain", ns_steps=None, orders=(1, 16),
+             batch=65536, cache=None, device=None) -> int:
+    """Time the candidate engines for each order in ``orders`` (inclusive range
+    within 1..16) on the current device and stream and record the fastest for
+    later calls with the same dtype, method and precision.  ``cache``: a text
+    file whose entries for this device are loaded instead of measured (new
+    ones are appended).  Returns the number of orders measured."""
+    if ns_steps is None:
+        ns_steps = 1 if precision == "mixed" else 0
+    opts = L.make_opts(method, precision, ns_steps, True)
+    path = None if cache is None else str(cache).encode()
+    rc = L.lib().chol_autotune(_code_of(dtype), ctypes.byref(opts), int(orders[0]), int(orders[1]),
+                               int(batch), path, _stream(device))
+    if rc < 0:
+        L.check("chol_autotune", rc)
+    return int(rc)
+
+
+def tuned_engine(dtype, n, *, method="chol", precision="plain") -> int:
+    """The recorded engine for order n (0 = built-in choice)."""
+    opts = L.make_opts(method, precision, 0, True)
+    rc = L.lib().chol_tuned_engine(_code_of(dtype), ctypes.byref(opts), int(n))
+    if rc < 0:
+        L.check("chol_tuned_engine", rc)
+    return int(rc)
+
+
+def autotune_clear() -> None:
+    """Forget every recorded engine choice."""
+    L.lib().chol_autotune_clear()
 
 
 def inverse_backward(X: torch.Tensor, G: torch.Tensor) -> torch.Tensor:

@@ -50,6 +50,11 @@ int check_opts(const ci_opts& o, int dtype)
 hipError_t run_small(int dtype, int64_t n, int op, int method, int mixed, const ci::BatchArgs& p,
                      hipStream_t s)
 {
+    if (op == ci::OP_INV) {
+        const int eng = ci::tuned_engine(dtype, mixed, method, (int)n);
+        if (eng != ci::ENG_DEFAULT)
+            return ci::launch_engine(eng, dtype, (int)n, op, method, mixed, p, s);
+    }
     if (n <= ci::tpm_nmax(dtype, mixed)) return ci::launch_tpm(dtype, (int)n, op, method, mixed, p, s);
     return ci::launch_group(dtype, (int)n, op, method, mixed, p, s);
 }
@@ -209,5 +214,29 @@ const char* chol_status_string(int code)
 }
 
 const char* chol_version(void) { return "cholinv 0.1 (gfx950)"; }
+
+int chol_autotune(int dtype, const ci_opts* opts, int n_lo, int n_hi, int64_t batch,
+                  const char* cache_path, void* stream)
+{
+    if (!valid_dtype(dtype)) return -1;
+    ci_opts o = opts ? *opts : default_opts();
+    if (check_opts(o, dtype)) return -2;
+    if (n_lo < 1 || n_lo > 16) return -3;
+    if (n_hi < n_lo || n_hi > 16) return -4;
+    if (batch < 1) return -5;
+    return ci::autotune(dtype, o.precision == CI_MIXED, o.method, o.ns_steps, n_lo, n_hi, batch,
+                        cache_path, (hipStream_t)stream);
+}
+
+int chol_tuned_engine(int dtype, const ci_opts* opts, int n)
+{
+    if (!valid_dtype(dtype)) return -1;
+    ci_opts o = opts ? *opts : default_opts();
+    if (check_opts(o, dtype)) return -2;
+    if (n < 0 || n > CI_SMALL_NMAX) return -3;
+    return ci::tuned_engine(dtype, o.precision == CI_MIXED, o.method, n);
+}
+
+void chol_autotune_clear(void) { ci::autotune_clear(); }
 
 }  // extern "C"

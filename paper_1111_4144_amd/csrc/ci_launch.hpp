@@ -42,7 +42,27 @@ struct BatchArgs {
     void* dout;        // LDL pivots (OP_LDL_FACTOR)
     int variant = VARIANT_AUTO;
     int group = 0;     // lanes per matrix for the group kernels (0 = default)
+    int ns_engine = -1;  // NS_ENGINE_* for the group kernels (-1 = process default)
 };
+
+// Engines the autotuner chooses between (orders <= 16).
+enum {
+    ENG_DEFAULT = 0,
+    ENG_TPM_DIRECT = 1,
+    ENG_TPM_STAGED = 2,
+    ENG_TPM_PERSIST = 3,
+    ENG_GROUP_LANES = 4,
+    ENG_GROUP_MFMA = 5
+};
+// Recorded choice for (dtype, mixed, method, n), ENG_DEFAULT if none.
+int tuned_engine(int dtype, int mixed, int method, int n);
+hipError_t launch_engine(int engine, int dtype, int n, int op, int method, int mixed, BatchArgs p,
+                         hipStream_t s);
+// Times the candidates for orders n_lo..n_hi; returns the number of orders
+// measured (>= 0) or a negative code.
+int autotune(int dtype, int mixed, int method, int ns_steps, int n_lo, int n_hi, int64_t batch,
+             const char* cache_path, hipStream_t s);
+void autotune_clear();
 
 int tpm_nmax(int dtype, int mixed);
 

@@ -8,7 +8,8 @@ hipError_t launch_group_f32(int n, int op, int method, int mixed, const BatchArg
                               hipStream_t s)
 {
     if (n <= 16) {
-        if (op == OP_INV && mixed && ns_engine() == NS_ENGINE_MFMA)
+        const int eng = p.ns_engine >= 0 ? p.ns_engine : ns_engine();
+        if (op == OP_INV && mixed && eng == NS_ENGINE_MFMA)
             return group16_mfma_run<float>(p, n, method, s);
         return group_run_ops<float, 16, 16>(n, op, method, mixed, p, s);
     }

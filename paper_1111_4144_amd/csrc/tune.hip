@@ -1,0 +1,211 @@
+// tune.hip -- the autotuner of the small-order engines.
+//
+// For orders up to 16 several kernels can invert a batch: the one-lane-per-
+// matrix kernels with direct loads, one-shot LDS staging or persistent
+// staging (orders up to the per-type register limit), and the 16-lane group
+// kernels with the Newton-Schulz step on the lane groups or on MFMA (mixed
+// precision).  chol_autotune times every candidate for each order of a range
+// on a synthetic batch on the caller's device and stream and records the
+// fastest; run_small consults the record.  Choices can be persisted in a text
+// cache keyed by the device (name and compute-unit count), so later processes
+// load them instead of measuring.  Ties within 1% go to the lower engine
+// number, so the choice is reproducible.
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "ci_launch.hpp"
+#include "ci_types.hpp"
+#include "cholinv.h"
+
+namespace ci {
+
+namespace {
+
+std::mutex g_mu;
+// [dtype][mixed][method][n] -> engine (0 = built-in default)
+int g_table[4][2][2][65];
+
+std::string device_key()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return "unknown";
+    std::string name = prop.gcnArchName;
+    for (char& c : name)
+        if (c == ' ') c = '_';
+    return name + ":" + std::to_string(prop.multiProcessorCount);
+}
+
+// Diagonally dominant Hermitian matrices: a_ii = n + 1, a_ij = 1/(1 + i + j)
+// (+ an imaginary part (j - i)/(8 n) above the diagonal for complex types).
+template <class V>
+__global__ void k_tune_fill(V* a, int64_t batch, int n)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= batch * n * n) return;
+    const int i = (int)((e / n) % n), j = (int)(e % n);
+    using R = typename vt<V>::real;
+    const R re = (i == j) ? R(n + 1) : R(1) / R(1 + i + j);
+    V v = mk<V>(re);
+    if constexpr (vt<V>::cplx) {
+        if (i != j) v.im = (j > i ? R(1) : R(-1)) * R(j > i ? j - i : i - j) / R(8 * n);
+    }
+    a[e] = v;
+}
+
+hipError_t fill(int dtype, void* a, int64_t batch, int n, hipStream_t s)
+{
+    const unsigned blocks = (unsigned)((batch * n * n + 255) / 256);
+    switch (dtype) {
+    case DT_F32: hipLaunchKernelGGL(k_tune_fill<float>, dim3(blocks), dim3(256), 0, s, (float*)a, batch, n); break;
+    case DT_F64: hipLaunchKernelGGL(k_tune_fill<double>, dim3(blocks), dim3(256), 0, s, (double*)a, batch, n); break;
+    case DT_C64: hipLaunchKernelGGL(k_tune_fill<cf>, dim3(blocks), dim3(256), 0, s, (cf*)a, batch, n); break;
+    default: hipLaunchKernelGGL(k_tune_fill<cd>, dim3(blocks), dim3(256), 0, s, (cd*)a, batch, n); break;
+    }
+    return hipGetLastError();
+}
+
+size_t elem_size(int dtype) { return dtype == DT_F32 ? 4 : (dtype == DT_C128 ? 16 : 8); }
+
+// Candidates for (dtype, mixed, n), in engine order.
+int candidates(int dtype, int mixed, int n, int* out)
+{
+    int k = 0;
+    if (n <= tpm_nmax(dtype, mixed)) {
+        out[k++] = ENG_TPM_DIRECT;
+        out[k++] = ENG_TPM_STAGED;
+        out[k++] = ENG_TPM_PERSIST;
+    }
+    if (n <= 16) {
+        out[k++] = ENG_GROUP_LANES;
+        if (mixed && (dtype == DT_F32 || dtype == DT_C64)) out[k++] = ENG_GROUP_MFMA;
+    }
+    return k;
+}
+
+bool load_cache(const char* path, const std::string& dev, int dtype, int mixed, int method,
+                int n_lo, int n_hi, bool* have)
+{
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    while (std::fgets(line, sizeof line, f)) {
+        char dname[256];
+        int d, p, m, n, e;
+        double us;
+        if (std::sscanf(line, "cholinv-tune v1 %255s %d %d %d %d %d %lf", dname, &d, &p, &m, &n,
+                        &e, &us) != 7)
+            continue;
+        if (dev != dname || d != dtype || p != mixed || m != method || n < n_lo || n > n_hi)
+            continue;
+        if (e < ENG_DEFAULT || e > ENG_GROUP_MFMA) continue;
+        g_table[dtype][mixed][method][n] = e;
+        have[n] = true;
+    }
+    std::fclose(f);
+    return true;
+}
+
+}  // namespace
+
+int tuned_engine(int dtype, int mixed, int method, int n)
+{
+    if (dtype < 0 || dtype > 3 || n < 0 || n > 64) return ENG_DEFAULT;
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_table[dtype][mixed ? 1 : 0][method ? 1 : 0][n];
+}
+
+// Launch one candidate engine on a uniform dense batch.
+hipError_t launch_engine(int engine, int dtype, int n, int op, int method, int mixed, BatchArgs p,
+                         hipStream_t s)
+{
+    switch (engine) {
+    case ENG_TPM_DIRECT: p.variant = VARIANT_DIRECT; return launch_tpm(dtype, n, op, method, mixed, p, s);
+    case ENG_TPM_STAGED: p.variant = VARIANT_STAGED; return launch_tpm(dtype, n, op, method, mixed, p, s);
+    case ENG_TPM_PERSIST: p.variant = VARIANT_PERSIST; return launch_tpm(dtype, n, op, method, mixed, p, s);
+    case ENG_GROUP_LANES: p.ns_engine = NS_ENGINE_LANES; return launch_group(dtype, n, op, method, mixed, p, s);
+    case ENG_GROUP_MFMA: p.ns_engine = NS_ENGINE_MFMA; return launch_group(dtype, n, op, method, mixed, p, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int autotune(int dtype, int mixed, int method, int ns_steps, int n_lo, int n_hi, int64_t batch,
+             const char* cache_path, hipStream_t s)
+{
+    const std::string dev = device_key();
+    bool have[65] = {false};
+    if (cache_path) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        load_cache(cache_path, dev, dtype, mixed, method, n_lo, n_hi, have);
+    }
+    const size_t es = elem_size(dtype);
+    void *a = nullptr, *x = nullptr, *info = nullptr;
+    const size_t bytes = (size_t)batch * n_hi * n_hi * es;
+    if (hipMalloc(&a, bytes) != hipSuccess) return -1000 - (int)hipErrorOutOfMemory;
+    if (hipMalloc(&x, bytes) != hipSuccess) { (void)hipFree(a); return -1000 - (int)hipErrorOutOfMemory; }
+    if (hipMalloc(&info, (size_t)batch * 4) != hipSuccess) {
+        (void)hipFree(a); (void)hipFree(x);
+        return -1000 - (int)hipErrorOutOfMemory;
+    }
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    int measured = 0;
+    hipError_t err = hipSuccess;
+    FILE* out = cache_path ? std::fopen(cache_path, "a") : nullptr;
+    for (int n = n_lo; n <= n_hi && err == hipSuccess; ++n) {
+        if (have[n]) continue;
+        int cand[8];
+        const int nc = candidates(dtype, mixed, n, cand);
+        if (nc < 2) continue;                      // nothing to choose
+        err = fill(dtype, a, batch, n, s);
+        BatchArgs p{a, x, batch, n, (int64_t)n * n, n, (int64_t)n * n, ns_steps, 1,
+                    (int32_t*)info, nullptr};
+        int best = ENG_DEFAULT;
+        float best_ms = 0.f;
+        for (int c = 0; c < nc && err == hipSuccess; ++c) {
+            err = launch_engine(cand[c], dtype, n, OP_INV, method, mixed, p, s);   // warm-up
+            if (err != hipSuccess) break;
+            (void)hipEventRecord(e0, s);
+            for (int r = 0; r < 3 && err == hipSuccess; ++r)
+                err = launch_engine(cand[c], dtype, n, OP_INV, method, mixed, p, s);
+            (void)hipEventRecord(e1, s);
+            if (err != hipSuccess) break;
+            err = hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (best == ENG_DEFAULT || ms < best_ms * 0.99f) {
+                best = cand[c];
+                best_ms = ms;
+            }
+        }
+        if (err != hipSuccess) break;
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            g_table[dtype][mixed][method][n] = best;
+        }
+        if (out)
+            std::fprintf(out, "cholinv-tune v1 %s %d %d %d %d %d %.3f\n", dev.c_str(), dtype, mixed,
+                         method, n, best, 1e3 * best_ms / 3);
+        ++measured;
+    }
+    if (out) std::fclose(out);
+    (void)hipStreamSynchronize(s);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(a);
+    (void)hipFree(x);
+    (void)hipFree(info);
+    return err == hipSuccess ? measured : -1000 - (int)err;
+}
+
+void autotune_clear()
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    std::memset(g_table, 0, sizeof g_table);
+}
+
+}  // namespace ci

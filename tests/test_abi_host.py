@@ -23,7 +23,7 @@ def test_header_declares_exactly_the_exported_names():
     from paper_1111_4144_amd import _lib as L
     with open(os.path.join(ROOT, "include", "cholinv.h")) as f:
         hdr = f.read()
-    declared = set(re.findall(r"^(?:int|size_t|const char\*)\s+(\w+)\(", hdr, re.M))
+    declared = set(re.findall(r"^(?:int|size_t|void|const char\*)\s+(\w+)\(", hdr, re.M))
     assert declared == set(L.EXPORTS)
 
 
