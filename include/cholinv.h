@@ -98,6 +98,8 @@ typedef struct {
  *   work, work_bytes  scratch (size from chol_workspace_size(CI_FN_FACTOR,..))
  * On return the upper triangle of each A holds R (real positive diagonal);
  * the strict lower triangle is untouched.  Precision: CI_PLAIN semantics.
+ * The blocked path (batch == 1, n > CI_SMALL_NMAX) needs lda == n and a real
+ * type (else CI_ERR_UNSUPPORTED).
  */
 int chol_factor(int dtype, int64_t batch, int64_t n, void* a, int64_t lda, int64_t stride,
                 int32_t* info, void* work, size_t work_bytes, void* stream);
@@ -128,9 +130,15 @@ int ldl_factor(int dtype, int64_t batch, int64_t n, void* a, int64_t lda, int64_
  *   work      device scratch of work_bytes >= chol_workspace_size(CI_FN_INVERSE, ...)
  *   info      device int32[1] or NULL
  * For n > CI_SMALL_NMAX the blocked path runs: right-looking blocked Cholesky
- * with MFMA trailing updates, then the blocked form of the Section IV
- * back-substitution (GEMMs against the already known trailing block of X);
- * only CI_METHOD_CHOL and real types are supported there.
+ * with MFMA trailing updates (mixed precision: FP64 pivot accumulators), then
+ * the inverse of R by block columns and the upper half of X = R^{-1} R^{-T}
+ * as one MFMA product (the same n^3/2 multiplies as Section IV, reading
+ * "zero-skipping triangular inverse"; the block form of the Section IV
+ * recurrence itself is selected by the environment variable
+ * CHOLINV_LARGE_INVERSE=blocked_iv), then the Newton-Schulz steps as an FP64
+ * and an FP32 MFMA product.  There only CI_METHOD_CHOL and real types
+ * (CI_F32, CI_F64) are supported (else CI_ERR_UNSUPPORTED), x must not equal
+ * a, and X is always written in full (fill_lower is ignored).
  */
 int chol_inverse(int dtype, int64_t n, const void* a, int64_t lda, void* x, int64_t ldx,
                  const ci_opts* opts, void* work, size_t work_bytes, int32_t* info,
@@ -149,8 +157,14 @@ int chol_inverse(int dtype, int64_t n, const void* a, int64_t lda, void* x, int6
  *   n_dev, offsets_dev  device int32[batch] / int64[batch] (varlen only)
  *   work        device scratch (varlen: the bucketed work list lives here)
  * Every matrix of a varlen batch is processed by the kernel of its size
- * bucket within a single persistent launch (after a small device-side
- * bucketing prologue), so the call is capturable in a HIP graph.
+ * bucket: after a small device-side bucketing prologue (largest orders
+ * first), one persistent launch takes the orders 33..64 and one the rest;
+ * nothing synchronises with the host, so the call is capturable in a HIP
+ * graph.  Varlen batches support the real types (CI_F32, CI_F64; others give
+ * CI_ERR_UNSUPPORTED); a matrix whose order is outside 0..n_max gets
+ * info[b] = -1 and its X is left untouched; order 0 gives info[b] = 0.
+ * For uniform batches of order <= 16 the kernel is the one recorded by
+ * chol_autotune for (dtype, precision, method, order), if any.
  */
 int chol_inverse_batched(int dtype, int64_t batch, int64_t n_uniform, const int32_t* n_dev,
                          const int64_t* offsets_dev, int64_t n_max, const void* a,
