@@ -245,7 +245,8 @@ def main():
     # engine choice per order, measured on this device before any timing
     tuned = {}
     for n in (8, 16):
-        api.autotune(torch.complex64, precision="mixed", ns_steps=1, orders=(n, n), batch=65536)
+        api.autotune(torch.complex64, precision="mixed", ns_steps=1, orders=(n, n),
+                     batch=COUNT_PER_ORDER)
         tuned[n] = api.tuned_engine(torch.complex64, n, precision="mixed")
 
     t_gen = time.perf_counter()

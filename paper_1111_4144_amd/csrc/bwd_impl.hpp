@@ -16,6 +16,7 @@
 #pragma once
 
 #include "group_impl.hpp"
+#include "mfma.hpp"
 #include "tpm_impl.hpp"
 #include "wpm_impl.hpp"
 
@@ -167,10 +168,134 @@ k_bwd_lds(const V* __restrict__ x, const V* __restrict__ g, V* __restrict__ ga, 
     }
 }
 
+// Orders 9..16, FP32 element types: both products on the matrix cores.  One
+// wave owns four matrices; X and Gh are staged in LDS (rows padded to 17),
+// T = Gh X is one MFMA 16 x 16 x 4 chain per matrix (complex: four real
+// products), and it lands in the FP32 accumulator layout (lane (g, c) holds
+// T[4 g + v][c]), which is the B operand of gA = -X T when step t takes
+// k = 4 g + t.  The upper half of gA is staged back through LDS and written
+// with its conjugate mirror.
+constexpr int B16_LD = 17;
+constexpr int B16_MAT = 16 * B16_LD;
+
+CI_D float b16_re(float v) { return v; }
+CI_D float b16_re(cf v) { return v.re; }
+CI_D float b16_im(float) { return 0.f; }
+CI_D float b16_im(cf v) { return v.im; }
+
+template <class V>
+__global__ void __launch_bounds__(64)
+k_bwd16_mfma(const V* __restrict__ x, const V* __restrict__ g, V* __restrict__ ga, int64_t batch,
+             int n, int64_t stride)
+{
+    using R = typename vt<V>::real;
+    constexpr bool C = vt<V>::cplx;
+    __shared__ __align__(16) V Xs[4 * B16_MAT];
+    __shared__ __align__(16) V Hs[4 * B16_MAT];
+    const int lane = threadIdx.x;
+    const int lg = lane / 16, lc = lane % 16;
+    const int64_t b0 = (int64_t)blockIdx.x * 4;
+    // stage X and G (zero beyond n and past the batch): every load is issued
+    // before the first LDS store, so the copy is not one latency per row
+    V xr[16], gr[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int e = lane + 64 * q;
+        const int m = e / 256, i = (e / 16) % 16, j = e % 16;
+        const int64_t b = b0 + m;
+        xr[q] = mk<V>(R(0));
+        gr[q] = mk<V>(R(0));
+        if (b < batch && i < n && j < n) {
+            xr[q] = x[b * stride + (int64_t)i * n + j];
+            gr[q] = g[b * stride + (int64_t)i * n + j];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int e = lane + 64 * q;
+        const int m = e / 256, i = (e / 16) % 16, j = e % 16;
+        Xs[m * B16_MAT + i * B16_LD + j] = xr[q];
+        Hs[m * B16_MAT + i * B16_LD + j] = gr[q];
+    }
+    __syncthreads();
+    // Gh = (G + G^H) / 2 in place: each unordered pair (i <= j) by one lane
+    for (int e = lane; e < 4 * 136; e += 64) {
+        const int m = e / 136;
+        int r = e % 136, i = 0;
+        while (r >= 16 - i) { r -= 16 - i; ++i; }
+        const int j = i + r;
+        V* H = Hs + m * B16_MAT;
+        const V gij = H[i * B16_LD + j], gji = H[j * B16_LD + i];
+        const V h = scal(add(gij, cj(gji)), R(0.5));
+        H[i * B16_LD + j] = (i == j) ? realpart_only(h) : h;
+        H[j * B16_LD + i] = (i == j) ? realpart_only(h) : cj(h);
+    }
+    __syncthreads();
+    for (int m = 0; m < 4; ++m) {
+        const V* Xm = Xs + m * B16_MAT;
+        const V* Hm = Hs + m * B16_MAT;
+        // T = Gh X
+        gf4 tr = {0, 0, 0, 0}, ti = {0, 0, 0, 0};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int k = 4 * t + lg;
+            const V hv = Hm[lc * B16_LD + k];      // Gh[c][k]
+            const V xv = Xm[k * B16_LD + lc];      // X[k][c]
+            tr = mfma16(b16_re(hv), b16_re(xv), tr);
+            if constexpr (C) {
+                tr = mfma16(-b16_im(hv), b16_im(xv), tr);
+                ti = mfma16(b16_re(hv), b16_im(xv), ti);
+                ti = mfma16(b16_im(hv), b16_re(xv), ti);
+            }
+        }
+        // gA = -X T, step t taking k = 4 lg + t (T's rows held by this lane)
+        gf4 ar = {0, 0, 0, 0}, ai = {0, 0, 0, 0};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const V xv = Xm[lc * B16_LD + 4 * lg + t];   // X[c][k]
+            ar = mfma16(-b16_re(xv), tr[t], ar);
+            if constexpr (C) {
+                ar = mfma16(b16_im(xv), ti[t], ar);
+                ai = mfma16(-b16_re(xv), ti[t], ai);
+                ai = mfma16(-b16_im(xv), tr[t], ai);
+            }
+        }
+        __syncthreads();                 // every lane has read matrix m's X
+        V* Om = Xs + m * B16_MAT;        // gA replaces X: rows 4 lg + v, column lc
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = 4 * lg + v;
+            V val;
+            if constexpr (C) val = V{ar[v], ai[v]};
+            else val = ar[v];
+            if (i == lc) Om[i * B16_LD + lc] = realpart_only(val);
+            if (i < lc) {
+                Om[i * B16_LD + lc] = val;
+                Om[lc * B16_LD + i] = cj(val);
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int e = lane + 64 * q;
+        const int m = e / 256, i = (e / 16) % 16, j = e % 16;
+        const int64_t b = b0 + m;
+        if (b < batch && i < n && j < n) ga[b * stride + (int64_t)i * n + j] = Xs[m * B16_MAT + i * B16_LD + j];
+    }
+}
+
 template <class V>
 static hipError_t bwd_run(int n, const void* x, const void* g, void* ga, int64_t batch,
                           int64_t stride, hipStream_t s)
 {
+    if constexpr (sizeof(typename vt<V>::real) == 4) {
+        if (n > 8 && n <= 16) {
+            hipLaunchKernelGGL(k_bwd16_mfma<V>, dim3((unsigned)((batch + 3) / 4)), dim3(64), 0, s,
+                               (const V*)x, (const V*)g, (V*)ga, batch, n, stride);
+            return hipGetLastError();
+        }
+    }
     auto grp = [&](auto kern, int G) {
         const int mpb = GROUP_BLOCK / G;
         hipLaunchKernelGGL(kern, dim3((unsigned)((batch + mpb - 1) / mpb)), dim3(GROUP_BLOCK), 0,

@@ -124,14 +124,24 @@ k_group16_mfma(const V* __restrict__ a, V* __restrict__ x, int64_t batch, int n,
     const int grp = lane / G, q = lane % G;
     const int64_t b0 = (int64_t)blockIdx.x * G16_MPW;
 
-    // ---- stage A (identity beyond n and for matrices past the batch) ----
-#pragma unroll 4
-    for (int e = lane; e < G16_MPW * 256; e += 64) {
-        const int m = e / 256, i = (e / 16) % 16, j = e % 16;
-        const int64_t b = b0 + m;
-        V v = mk<V>(R(i == j ? 1 : 0));
-        if (b < batch && i < n && j < n) v = a[b * sa + (int64_t)i * lda + j];
-        As[m * G16_MAT + i * G16_LD + j] = v;
+    // ---- stage A (identity beyond n and for matrices past the batch); all
+    // sixteen loads of a lane are issued before the first LDS store ----
+    {
+        V ar[16];
+#pragma unroll
+        for (int qq = 0; qq < 16; ++qq) {
+            const int e = lane + 64 * qq;
+            const int m = e / 256, i = (e / 16) % 16, j = e % 16;
+            const int64_t b = b0 + m;
+            ar[qq] = mk<V>(R(i == j ? 1 : 0));
+            if (b < batch && i < n && j < n) ar[qq] = a[b * sa + (int64_t)i * lda + j];
+        }
+#pragma unroll
+        for (int qq = 0; qq < 16; ++qq) {
+            const int e = lane + 64 * qq;
+            const int m = e / 256, i = (e / 16) % 16, j = e % 16;
+            As[m * G16_MAT + i * G16_LD + j] = ar[qq];
+        }
     }
     __syncthreads();
 
@@ -166,7 +176,7 @@ k_group16_mfma(const V* __restrict__ a, V* __restrict__ x, int64_t batch, int n,
         for (int m = 0; m < G16_MPW; ++m) g16_ns_step<V>(As + m * G16_MAT, Xs + m * G16_MAT, lane);
 
     // ---- store (NaN for a failed factorisation) ----
-#pragma unroll 4
+#pragma unroll
     for (int e = lane; e < G16_MPW * 256; e += 64) {
         const int m = e / 256, i = (e / 16) % 16, j = e % 16;
         const int64_t b = b0 + m;
