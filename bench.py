@@ -216,6 +216,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary workloads")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
     ap.add_argument("--no-large", action="store_true", help="skip the N=8192 / N=4096 workloads")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the built-in engine choice (no autotuning launches, e.g. for "
+                         "counter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB three times (the reference "
                          "kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -245,8 +248,9 @@ def main():
     # engine choice per order, measured on this device before any timing
     tuned = {}
     for n in (8, 16):
-        api.autotune(torch.complex64, precision="mixed", ns_steps=1, orders=(n, n),
-                     batch=COUNT_PER_ORDER)
+        if not args.no_tune:
+            api.autotune(torch.complex64, precision="mixed", ns_steps=1, orders=(n, n),
+                         batch=COUNT_PER_ORDER)
         tuned[n] = api.tuned_engine(torch.complex64, n, precision="mixed")
 
     t_gen = time.perf_counter()
