@@ -76,13 +76,42 @@ CI_D int bc32(int v, int k)
     return bc32_dispatch<G>(v, k, std::make_integer_sequence<int, G>{});
 }
 
+// 64-bit broadcast inside 16-lane rows: one v_mov_b64 with DPP row_newbcast.
+// The tied "old" operand is an unconstrained register from an empty asm (all
+// lanes are written, so its value never shows), which avoids a copy.
+template <int K>
+CI_D long bc64_16_k(long u)
+{
+    long old;
+    asm volatile("" : "=v"(old));
+    return __builtin_amdgcn_update_dpp(old, u, 0x150 + K, 0xf, 0xf, false);
+}
+template <int... Ks>
+CI_D long bc64_16_dispatch(long v, int k, std::integer_sequence<int, Ks...>)
+{
+    long r = v;
+    ((k == Ks ? (r = bc64_16_k<Ks>(v), 0) : 0), ...);
+    return r;
+}
+CI_D long bc64_16(long v, int k)
+{
+    return bc64_16_dispatch(v, k, std::make_integer_sequence<int, 16>{});
+}
+
 template <int G> CI_D float bc(float v, int k) { return __builtin_bit_cast(float, bc32<G>(__builtin_bit_cast(int, v), k)); }
 template <int G> CI_D double bc(double v, int k) {
-    const uint64_t u = __builtin_bit_cast(uint64_t, v);
-    const int lo = bc32<G>((int)(uint32_t)u, k), hi = bc32<G>((int)(uint32_t)(u >> 32), k);
-    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+    if constexpr (G == 16) {
+        return __builtin_bit_cast(double, bc64_16(__builtin_bit_cast(long, v), k));
+    } else {
+        const uint64_t u = __builtin_bit_cast(uint64_t, v);
+        const int lo = bc32<G>((int)(uint32_t)u, k), hi = bc32<G>((int)(uint32_t)(u >> 32), k);
+        return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+    }
 }
-template <int G> CI_D cf bc(cf v, int k) { return cf{bc<G>(v.re, k), bc<G>(v.im, k)}; }
+template <int G> CI_D cf bc(cf v, int k) {
+    if constexpr (G == 16) return __builtin_bit_cast(cf, bc64_16(__builtin_bit_cast(long, v), k));
+    else return cf{bc<G>(v.re, k), bc<G>(v.im, k)};
+}
 template <int G> CI_D cd bc(cd v, int k) { return cd{bc<G>(v.re, k), bc<G>(v.im, k)}; }
 template <int G> CI_D int bci(int v, int k) { return bc32<G>(v, k); }
 
