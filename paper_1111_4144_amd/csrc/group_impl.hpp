@@ -141,6 +141,38 @@ template <int G> CI_D cd bcr(cd v, int k) { return cd{bcr<G>(v.re, k), bcr<G>(v.
 template <class V>
 CI_D V sel(bool c, V a, V b) { return c ? a : b; }
 
+// Sum over the 16 lanes of a DPP row, every lane getting the total: quad
+// exchanges (xor 1, xor 2), then row_half_mirror (quad 0 <-> 1, 2 <-> 3) and
+// row_mirror (half 0 <-> 1).  Each step adds a value and its partner's in
+// either order, so all lanes hold bitwise the same sum.
+template <int CTRL>
+CI_D float dpp_f(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xf,
+                                                              0xf, false));
+}
+template <int CTRL>
+CI_D double dpp_f(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+template <class T>
+CI_D T row_sum16(T v)
+{
+    v += dpp_f<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_f<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_f<0x141>(v);   // row_half_mirror
+    v += dpp_f<0x140>(v);   // row_mirror
+    return v;
+}
+CI_D float row_sum16v(float v) { return row_sum16(v); }
+CI_D double row_sum16v(double v) { return row_sum16(v); }
+CI_D cf row_sum16v(cf v) { return cf{row_sum16(v.re), row_sum16(v.im)}; }
+CI_D cd row_sum16v(cd v) { return cd{row_sum16(v.re), row_sum16(v.im)}; }
+
 // re(conj(a) b) in precision P (products of FP32 values are exact in FP64)
 template <class P> CI_D P dot_re(float a, float b) { return (P)a * (P)b; }
 template <class P> CI_D P dot_re(double a, double b) { return (P)(a * b); }
@@ -257,15 +289,24 @@ CI_D int group_core(V (&M)[S][NB], P (&piv)[S], typename vt<V>::real (&dall)[NB]
             // (c) x_ii = s_i (s_i - sum_{k>i} r_ik conj(x_ik)) on the owner; row i
             // of R is still in place (it is replaced only below)
             V d = mk<V>(sall[i]);
+            if constexpr (S == 1 && G == 16) {
+                // lane k > i holds both r_ik (row i of its column of R) and x_ik
+                // (its xnew): one local product each, summed across the row
+                V prod = mk<V>(R(0));
+                madd(prod, M[0][i], cj(xnew[0]));
+                prod = (q > i) ? prod : mk<V>(R(0));
+                d = add(d, neg(row_sum16v(prod)));
+            } else {
 #pragma unroll
-            for (int k = i + 1; k < NB; ++k) {
-                // broadcast again rather than keep (a)'s broadcasts live across (b)
-                // (or the factorisation's)
-                V src = M[k / G][i];
-                opaque(src);
-                const V rik = bc<G>(src, k % G);
-                msub(d, rik, M[si][k]);
-                opaque(d);
+                for (int k = i + 1; k < NB; ++k) {
+                    // broadcast again rather than keep (a)'s broadcasts live across
+                    // (b) (or the factorisation's)
+                    V src = M[k / G][i];
+                    opaque(src);
+                    const V rik = bc<G>(src, k % G);
+                    msub(d, rik, M[si][k]);
+                    opaque(d);
+                }
             }
             d = realpart_only((METHOD == 0) ? scal(d, sall[i]) : d);
             // row i of X replaces row i of R
