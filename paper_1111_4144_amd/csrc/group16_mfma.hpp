@@ -11,8 +11,8 @@
 //                 values: every product is exact, the sums are FP64),
 //   F = X E       in FP32 (v_mfma_f32_16x16x4f32, E rounded to FP32),
 //   X <- X + F    upper half, diagonal real, lower half the conjugate mirror.
-// Complex products are four real products: (Ar + i Ai)(Xr + i Xi) =
-// Ar Xr - Ai Xi + i (Ar Xi + Ai Xr).  The residual accumulator lands in the
+// Complex products take three real products (Ar Xr, Ai Xi and
+// (Ar + Ai)(Xr + Xi)).  The residual accumulator lands in the
 // FP64 layout (lane holds E[g + 4 v][c]), which is directly the B operand of
 // the update when step v takes k = g + 4 v.
 #pragma once
@@ -45,41 +45,51 @@ CI_D void g16_ns_step(const V* __restrict__ As, V* __restrict__ Xs, int lane)
 {
     constexpr bool C = vt<V>::cplx;
     const int g = lane / 16, c = lane % 16;
-    gd4 er = {0, 0, 0, 0}, ei = {0, 0, 0, 0};
+    // complex products with three real products each:
+    //   Re(A X) = P1 - P2, Im(A X) = P3 - P1 - P2,
+    //   P1 = Ar Xr, P2 = Ai Xi, P3 = (Ar + Ai)(Xr + Xi)
+    // (the operand sums are exact or FP64-rounded for the residual; for the
+    // update they round in FP32 inside a correction of size ~kappa u)
+    gd4 p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         const int k = 4 * t + g;
         const V av = As[c * G16_LD + k];       // A[c][k]
         const V xv = Xs[k * G16_LD + c];       // X[k][c]
         const double ar = g16_re(av), xr = g16_re(xv);
-        er = mfma16(ar, xr, er);
+        p1 = mfma16(ar, xr, p1);
         if constexpr (C) {
             const double ai = g16_im(av), xi = g16_im(xv);
-            er = mfma16(-ai, xi, er);
-            ei = mfma16(ar, xi, ei);
-            ei = mfma16(ai, xr, ei);
+            p2 = mfma16(ai, xi, p2);
+            p3 = mfma16(ar + ai, xr + xi, p3);
         }
     }
     // E = I - A X; lane holds rows g + 4 v of column c
     float e_r[4], e_i[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        e_r[v] = (float)(((g + 4 * v) == c ? 1.0 : 0.0) - er[v]);
-        e_i[v] = C ? (float)(-ei[v]) : 0.f;
+        const double axr = C ? p1[v] - p2[v] : p1[v];
+        e_r[v] = (float)(((g + 4 * v) == c ? 1.0 : 0.0) - axr);
+        e_i[v] = C ? (float)(-(p3[v] - p1[v] - p2[v])) : 0.f;
     }
-    gf4 fr = {0, 0, 0, 0}, fi = {0, 0, 0, 0};
+    gf4 q1 = {0, 0, 0, 0}, q2 = {0, 0, 0, 0}, q3 = {0, 0, 0, 0};
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         const int k = g + 4 * t;
         const V xv = Xs[c * G16_LD + k];       // X[c][k]
         const float xr = g16_re(xv);
-        fr = mfma16(xr, e_r[t], fr);
+        q1 = mfma16(xr, e_r[t], q1);
         if constexpr (C) {
             const float xi = g16_im(xv);
-            fr = mfma16(-xi, e_i[t], fr);
-            fi = mfma16(xr, e_i[t], fi);
-            fi = mfma16(xi, e_r[t], fi);
+            q2 = mfma16(xi, e_i[t], q2);
+            q3 = mfma16(xr + xi, e_r[t] + e_i[t], q3);
         }
+    }
+    gf4 fr, fi;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        fr[v] = C ? q1[v] - q2[v] : q1[v];
+        fi[v] = C ? q3[v] - q1[v] - q2[v] : 0.f;
     }
     // F lands as rows 4 g + v of column c: X + F on the upper half
     V xn[4];
