@@ -149,6 +149,32 @@ CI_D double rcp_est(double v)
 }
 CI_D float rcp_est(float v) { return __builtin_amdgcn_rcpf(v); }
 
+// Sum over TPC = 1, 2 or 4 adjacent lanes (a quad), every lane getting the
+// total, with DPP quad permutes (xor 1, then xor 2); partners add in either
+// order, so the lanes hold bitwise the same sum.
+template <int CTRL>
+CI_D float quad_dpp(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xf,
+                                                              0xf, false));
+}
+template <int CTRL>
+CI_D double quad_dpp(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+template <int TPC, class T>
+CI_D T quad_sum(T v)
+{
+    static_assert(TPC == 1 || TPC == 2 || TPC == 4, "lanes per column");
+    if constexpr (TPC >= 2) v += quad_dpp<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    if constexpr (TPC == 4) v += quad_dpp<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    return v;
+}
+
 CI_D bool pivot_ok(double v) { return v > 0.0 && v < __builtin_inf(); }
 CI_D bool pivot_ok(float v)  { return v > 0.f && v < __builtin_inff(); }
 

@@ -87,14 +87,21 @@ __device__ __forceinline__ void lg_ldv(const T* q, T (&v)[LG_P<T>])
 // are combined with lane shuffles, so the serial steps are spread over
 // LG_TPC times more waves.
 constexpr int LG_TPC = 4;
+template <class T> constexpr int LG_SB = 32;          // sub-block of the diagonal factor
 
 template <class T>
 __device__ __forceinline__ T lg_colsum(T v)
 {
-#pragma unroll
-    for (int o = 1; o < LG_TPC; o <<= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    return quad_sum<LG_TPC>(v);
 }
+
+// LDS of the diagonal factor kernel: R and Y (NB x LD each), 1/r_ii and r_ii,
+// then the FP64 pivot accumulators of the panel.
+template <class T> constexpr size_t lg_diag_dl_offset()
+{
+    return ((size_t)(2 * LG_NB<T> * LG_LD<T> + 2 * LG_NB<T>) * sizeof(T) + 15) / 16 * 16;
+}
+template <class T> constexpr size_t lg_diag_smem() { return lg_diag_dl_offset<T>() + LG_NB<T> * 8; }
 
 template <class T, int MIXED>
 __global__ void __launch_bounds__(LG_NB<T> * LG_TPC)
@@ -105,7 +112,9 @@ k_lg_diag_factor(T* __restrict__ W, int64_t ldw, int r0, int nl, const double* _
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* Rm = reinterpret_cast<T*>(smem_raw);
     T* Ym = Rm + NB * LD;
-    T* sv = Ym + NB * LD;                          // 1/r_ii, then a pivot flag
+    T* sv = Ym + NB * LD;                          // 1/r_ii
+    T* rd = sv + NB;                               // r_ii
+    double* dl = reinterpret_cast<double*>(smem_raw + lg_diag_dl_offset<T>());   // FP64 pivots
     const int j = threadIdx.x / LG_TPC, h = threadIdx.x % LG_TPC;
     T* Wb = W + (int64_t)r0 * ldw + r0;
     for (int k = h; k < NB; k += LG_TPC) {
@@ -114,59 +123,114 @@ k_lg_diag_factor(T* __restrict__ W, int64_t ldw, int r0, int nl, const double* _
         Rm[j * LD + k] = (k <= j) ? v : T(0);
         Ym[j * LD + k] = T(0);
     }
+    if (MIXED && h == 0) dl[j] = (j < nl) ? dacc[r0 + j] : 1.0;
     __syncthreads();
     int fail = 0;
-    // FP64 sum of squares of column j of R above the diagonal, accumulated as
-    // its entries are produced (the pivot of step j is dacc_j minus it)
-    double sq = 0.0;
-    // this column's FP64 pivot accumulator, read once (a global load inside
-    // the serial loop would put its latency on every step)
-    const double dj = (MIXED && j < nl) ? dacc[r0 + j] : 1.0;
-    for (int i = 0; i < NB; ++i) {
-        const T* ci = Rm + i * LD;
-        const T* cj = Rm + j * LD;
-        // a_ij - sum_{k<i} r_ki r_kj: whole packets (this lane's share), then
-        // the partial one
-        const int full = i / P;
-        T dot = T(0);
-        for (int p = h; p < full; p += LG_TPC) {
-            T u[P], w[P];
-            lg_ldv(ci + p * P, u);
-            lg_ldv(cj + p * P, w);
+    // Sub-blocks of LG_SB columns: rows of a sub-block by the Crout recurrence
+    // over the sub-block's own earlier rows only, then the finished sub-block
+    // applied to the rest of the block as one rank-LG_SB update (parallel over
+    // all lanes), with the FP64 pivot accumulators updated the same way.
+    // Every lane forms the pivot of row i itself (column i's squares ride
+    // along in the same packet loop), so one barrier per row suffices; row
+    // i's diagonal goes to rd[] and into R only after the loop (column i is
+    // read by every lane during step i).
+    constexpr int SB = LG_SB<T>;
+    for (int b0 = 0; b0 < NB; b0 += SB) {
+        for (int i = b0; i < b0 + SB; ++i) {
+            const T* ci = Rm + i * LD;
+            const T* cj = Rm + j * LD;
+            const int p0 = b0 / P, full = i / P;
+            T dot = T(0), sii = T(0);
+            double s64 = 0.0;
+            for (int p = p0 + h; p < full; p += LG_TPC) {
+                T u[P], w[P];
+                lg_ldv(ci + p * P, u);
+                lg_ldv(cj + p * P, w);
 #pragma unroll
-            for (int c = 0; c < P; ++c) dot += u[c] * w[c];
-        }
-        if (h == 0)
-            for (int k = full * P; k < i; ++k) dot += ci[k] * cj[k];
-        dot = lg_colsum(dot);
-        const T acc = cj[i] - dot;
-        __syncthreads();
-        if (j == i && h == 0) {
-            const double piv = MIXED ? (dj - sq) : (double)acc;
+                for (int c = 0; c < P; ++c) {
+                    dot += u[c] * w[c];
+                    if (MIXED) s64 = fma((double)u[c], (double)u[c], s64);
+                    else sii += u[c] * u[c];
+                }
+            }
+            if (h == 0) {
+                for (int k = full * P; k < i; ++k) {
+                    const T u = ci[k];
+                    dot += u * cj[k];
+                    if (MIXED) s64 = fma((double)u, (double)u, s64);
+                    else sii += u * u;
+                }
+            }
+            dot = lg_colsum(dot);
+            const T acc = cj[i] - dot;
+            double piv;
+            if (MIXED) piv = dl[i] - lg_colsum(s64);
+            else piv = (double)(ci[i] - lg_colsum(sii));
             const bool ok = piv > 0.0 && piv < __builtin_inf();
-            const double r = sqrt(piv);
-            Rm[i * LD + i] = (T)r;
-            sv[i] = (T)(1.0 / r);
-            sv[NB] = ok ? T(1) : T(0);
+            if (!ok && !fail && i < nl) fail = i + 1;
+            T rii, si;
+            if constexpr (sizeof(T) == 4) {
+                double r, y;
+                sqrt_rsqrt_est(piv, r, y);       // FP32 results
+                rii = (T)r;
+                si = (T)y;
+            } else {
+                const double r = sqrt(piv);
+                rii = (T)r;
+                si = (T)(1.0 / r);
+            }
+            if (h == 0) {
+                if (j > i) Rm[j * LD + i] = acc * si;
+                if (j == i) {
+                    sv[i] = si;
+                    rd[i] = rii;
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        if (!(sv[NB] > T(0)) && !fail && i < nl) fail = i + 1;
-        if (j > i) {
-            const T rij = acc * sv[i];
-            if (h == 0) Rm[j * LD + i] = rij;
-            if (MIXED) sq = fma((double)rij, (double)rij, sq);
+        const int b1 = b0 + SB;
+        if (b1 < NB && j >= b1) {
+            // a_kj -= sum_{m in sub-block} r_mk r_mj, b1 <= k <= j (this lane's rows)
+            const T* cj = Rm + j * LD;
+            T wj[SB];
+#pragma unroll
+            for (int m = 0; m < SB; m += P) lg_ldv(cj + b0 + m, *reinterpret_cast<T(*)[P]>(wj + m));
+            for (int k = b1 + h; k <= j; k += LG_TPC) {
+                const T* ck = Rm + k * LD + b0;
+                T part = T(0);
+#pragma unroll
+                for (int m = 0; m < SB; m += P) {
+                    T u[P];
+                    lg_ldv(ck + m, u);
+#pragma unroll
+                    for (int c = 0; c < P; ++c) part += u[c] * wj[m + c];
+                }
+                Rm[j * LD + k] -= part;
+            }
+            if (MIXED && h == 0) {
+                double q = 0.0;
+#pragma unroll
+                for (int m = 0; m < SB; ++m) q = fma((double)wj[m], (double)wj[m], q);
+                dl[j] -= q;
+            }
         }
         __syncthreads();
     }
+    if (h == 0) Rm[j * LD + j] = rd[j];
+    __syncthreads();
     if (j < nl)
         for (int k = h; k <= j; k += LG_TPC) Wb[(int64_t)k * ldw + j] = Rm[j * LD + k];
-    // Y = R^{-1}, column j: y_jj = 1/r_jj, y_ij = -(1/r_ii) sum_{k=i+1..j} r_ik y_kj.
-    // Entries not computed yet are zero, and R is zero below its diagonal, so
-    // the packets may start below i+1.  The lanes of column j are adjacent in
-    // one wave, so lane 0's write of y_ij precedes every lane's later reads.
+    // Y = R^{-1} by sub-blocks.  Diagonal sub-blocks first, all at once: in
+    // column j, y_jj = 1/r_jj and y_ij = -(1/r_ii) sum_{k=i+1..j} r_ik y_kj for
+    // i down to the sub-block's first row (entries not computed yet are zero,
+    // and R is zero below its diagonal, so the packets may start below i+1;
+    // the lanes of column j are adjacent in one wave, so lane 0's write of
+    // y_ij precedes every lane's later reads).  Then block rows bottom-up:
+    // Y_{I,>I} = -Y_II (R_{I,>I} Y_{>I,>I}), each a parallel stage.
     if (h == 0) Ym[j * LD + j] = sv[j];
-    for (int i = NB - 2; i >= 0; --i) {
-        if (i < j) {
+    {
+        const int bj = (j / SB) * SB;
+        for (int i = j - 1; i >= bj; --i) {
             T dot = T(0);
             for (int p = (i + 1) / P + h; p <= j / P; p += LG_TPC) {
                 T w[P];
@@ -177,6 +241,40 @@ k_lg_diag_factor(T* __restrict__ W, int64_t ldw, int r0, int nl, const double* _
             dot = lg_colsum(dot);
             if (h == 0) Ym[j * LD + i] = -sv[i] * dot;
         }
+    }
+    __syncthreads();
+    constexpr int NT = NB * LG_TPC;
+    constexpr int PER = (SB * (NB - SB) + NT - 1) / NT;
+    for (int a0 = NB - 2 * SB; a0 >= 0; a0 -= SB) {
+        const int b1 = a0 + SB, cnt = SB * (NB - b1);
+        // t_ij = sum_{k=b1..j} r_ik y_kj into the (still zero) Y_{I,>I} block
+        for (int e = threadIdx.x; e < cnt; e += NT) {
+            const int i = a0 + e % SB, jj = b1 + e / SB;
+            T t = T(0);
+            for (int k = b1; k <= jj; ++k) t += Rm[k * LD + i] * Ym[jj * LD + k];
+            Ym[jj * LD + i] = t;
+        }
+        __syncthreads();
+        // y_ij = -sum_{m=i..b1-1} (Y_II)_im t_mj
+        T val[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = threadIdx.x + q * NT;
+            val[q] = T(0);
+            if (e < cnt) {
+                const int i = a0 + e % SB, jj = b1 + e / SB;
+                T acc = T(0);
+                for (int m = i; m < b1; ++m) acc += Ym[m * LD + i] * Ym[jj * LD + m];
+                val[q] = -acc;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = threadIdx.x + q * NT;
+            if (e < cnt) Ym[(b1 + e / SB) * LD + a0 + e % SB] = val[q];
+        }
+        __syncthreads();
     }
     for (int i = h; i < NB; i += LG_TPC) rinv[(int64_t)i * NB + j] = (i <= j) ? Ym[j * LD + i] : T(0);
     if (threadIdx.x == 0 && fail && info && info[0] == 0) info[0] = r0 + fail;
@@ -428,7 +526,7 @@ template <class T, int MIXED>
 static hipError_t lg_factor(T* W, int64_t n, double* dacc, T* rinv, int32_t* info, hipStream_t s)
 {
     constexpr int NB = LG_NB<T>;
-    const size_t smem = (size_t)(2 * NB * LG_LD<T> + NB + 4) * sizeof(T);
+    const size_t smem = lg_diag_smem<T>();
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void*)k_lg_diag_factor<T, MIXED>,

@@ -70,18 +70,8 @@ CI_D void pk_loop(int p0, int p1, F fetch, B body)
 }
 
 // Sum over the TPC adjacent lanes that share a column.
-template <int TPC> CI_D float tpc_sum(float v)
-{
-#pragma unroll
-    for (int o = 1; o < TPC; o <<= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-template <int TPC> CI_D double tpc_sum(double v)
-{
-#pragma unroll
-    for (int o = 1; o < TPC; o <<= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
+template <int TPC> CI_D float tpc_sum(float v) { return quad_sum<TPC>(v); }
+template <int TPC> CI_D double tpc_sum(double v) { return quad_sum<TPC>(v); }
 template <int TPC> CI_D cf tpc_sum(cf v) { return cf{tpc_sum<TPC>(v.re), tpc_sum<TPC>(v.im)}; }
 template <int TPC> CI_D cd tpc_sum(cd v) { return cd{tpc_sum<TPC>(v.re), tpc_sum<TPC>(v.im)}; }
 
