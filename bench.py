@@ -216,6 +216,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary workloads")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
     ap.add_argument("--no-large", action="store_true", help="skip the N=8192 / N=4096 workloads")
+    ap.add_argument("--only", choices=["large", "varlen"], default=None,
+                    help="run only one secondary workload and print its figures (for profiling)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the built-in engine choice (no autotuning launches, e.g. for "
                          "counter runs)")
@@ -244,6 +246,12 @@ def main():
 
     import oracle as O
     from paper_1111_4144_amd import api, inputs as G
+
+    if args.only:
+        fn = {"large": lambda: large_workloads(torch, api, G, dev, max(2, args.steps // 4)),
+              "varlen": lambda: varlen_workload(torch, api, G, O, dev, max(3, args.steps // 2))}
+        print(json.dumps({"only": args.only, "details": fn[args.only]()}), flush=True)
+        return
 
     # engine choice per order, measured on this device before any timing
     tuned = {}
