@@ -42,19 +42,29 @@ __global__ void k_vl_init(VarlenPlan* plan)
     for (int i = threadIdx.x; i < (int)(sizeof(VarlenPlan) / sizeof(int)); i += blockDim.x) p[i] = 0;
 }
 
-__global__ void k_vl_count(const int32_t* __restrict__ ns, int64_t batch, int nmax,
-                           VarlenPlan* plan, int32_t* __restrict__ info)
+// Orders are counted per block in LDS first, so each block adds to a global
+// counter once per order present instead of once per matrix.
+__global__ void __launch_bounds__(256)
+k_vl_count(const int32_t* __restrict__ ns, int64_t batch, int nmax, VarlenPlan* plan,
+           int32_t* __restrict__ info)
 {
+    __shared__ int local[65];
+    for (int t = threadIdx.x; t < 65; t += blockDim.x) local[t] = 0;
+    __syncthreads();
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= batch) return;
-    const int n = ns[b];
-    if (n < 0 || n > nmax) {
-        if (info) info[b] = -1;
-    } else if (n == 0) {
-        if (info) info[b] = 0;
-    } else {
-        atomicAdd(&plan->count[n], 1);
+    if (b < batch) {
+        const int n = ns[b];
+        if (n < 0 || n > nmax) {
+            if (info) info[b] = -1;
+        } else if (n == 0) {
+            if (info) info[b] = 0;
+        } else {
+            atomicAdd(&local[n], 1);
+        }
     }
+    __syncthreads();
+    for (int t = threadIdx.x; t < 65; t += blockDim.x)
+        if (local[t]) atomicAdd(&plan->count[t], local[t]);
 }
 
 __global__ void k_vl_scan(VarlenPlan* plan)
@@ -76,15 +86,28 @@ __global__ void k_vl_scan(VarlenPlan* plan)
     plan->next_big = 0;
 }
 
-__global__ void k_vl_scatter(const int32_t* __restrict__ ns, int64_t batch, int nmax,
-                             VarlenPlan* plan, int32_t* __restrict__ sorted)
+// Each block reserves one contiguous range per order with a single global
+// atomic and places its matrices inside it with LDS atomics.  The order of
+// matrices within an order's range is therefore not the batch order; results
+// do not depend on it.
+__global__ void __launch_bounds__(256)
+k_vl_scatter(const int32_t* __restrict__ ns, int64_t batch, int nmax, VarlenPlan* plan,
+             int32_t* __restrict__ sorted)
 {
+    __shared__ int local[65], base[65];
+    for (int t = threadIdx.x; t < 65; t += blockDim.x) local[t] = 0;
+    __syncthreads();
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= batch) return;
-    const int n = ns[b];
-    if (n < 1 || n > nmax) return;
-    const int pos = plan->item_start[n] + atomicAdd(&plan->cursor[n], 1);
-    sorted[pos] = (int32_t)b;
+    int n = 0, slot = -1;
+    if (b < batch) {
+        n = ns[b];
+        if (n >= 1 && n <= nmax) slot = atomicAdd(&local[n], 1);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < 65; t += blockDim.x)
+        if (local[t]) base[t] = plan->item_start[t] + atomicAdd(&plan->cursor[t], local[t]);
+    __syncthreads();
+    if (slot >= 0) sorted[base[n] + slot] = (int32_t)b;
 }
 
 // One lane, one matrix of order N (dense, leading dimension N).
