@@ -99,7 +99,10 @@ CI_D void g16_ns_step(const V* __restrict__ As, V* __restrict__ Xs, int lane)
         const V xo = Xs[i * G16_LD + c];
         xn[v] = g16_make<V>(g16_re(xo) + fr[v], C ? g16_im(xo) + fi[v] : 0.f);
     }
-    __syncthreads();    // every lane has read X
+    // The workgroup is this one wave, whose LDS accesses complete in program
+    // order: the reads of X above precede these writes for every lane, and the
+    // writes precede any later read.  No workgroup barrier is needed, so the
+    // compiler may overlap the next matrix's loads with this one's products.
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int i = 4 * g + v;
@@ -109,7 +112,6 @@ CI_D void g16_ns_step(const V* __restrict__ As, V* __restrict__ Xs, int lane)
             Xs[c * G16_LD + i] = cj(xn[v]);
         }
     }
-    __syncthreads();
 }
 
 #ifndef CI_G16_WAVES
