@@ -6,7 +6,10 @@
 //     R_II = chol(A_II) and R_II^{-1}          one workgroup, LDS resident
 //     R_I,>I = R_II^{-T} A_I,>I                 GEMM with the explicit inverse
 //     A_>I,>I -= R_I,>I^T R_I,>I                 upper-only GEMM (SYRK)
-// Inversion (Section IV in block form, block rows bottom-up).  Row block I of
+// Inversion, default: M = R^{-1} by block columns (zero blocks skipped), then
+// the upper half of X = M M^T in one product (lg_trtri, lg_lauum).
+// Inversion, alternative (Section IV in block form, block rows bottom-up;
+// CHOLINV_LARGE_INVERSE=blocked_iv).  Row block I of
 // R X = B, with B lower triangular and its upper triangle S = diag(1/r_ii)
 // known, gives for J > I:  X_I,J = -R_II^{-1} (R_I,>I X-hat_>I,J) (B_I,J = 0),
 // and for the diagonal block the scalar recurrence of the small kernels with
@@ -498,11 +501,11 @@ static hipError_t gemm(int M, int N, int K, double alpha, const TA* A, int64_t l
 template <class T>
 static hipError_t gemm_splitk(int M, int N, int K, double alpha, const T* A, int64_t lda, int ta,
                               const T* B, int64_t ldb, int tb, T* C, int64_t ldc, T* part,
-                              int64_t cap, hipStream_t s, int tri = 0)
+                              int64_t cap, hipStream_t s, int tri = 0, int kmin = 64)
 {
     const int tiles = ((M + GT_M - 1) / GT_M) * ((N + GT_N - 1) / GT_N);
     int splits = (512 + tiles - 1) / tiles;
-    splits = std::min<int64_t>(splits, std::max(1, K / 64));
+    splits = std::min<int64_t>(splits, std::max(1, K / kmin));
     splits = (int)std::min<int64_t>(splits, cap / ((int64_t)M * N));
     if (splits <= 1)
         return gemm<T, T, T>(M, N, K, alpha, A, lda, ta, B, ldb, tb, 0.0, C, ldc, 0, s, tri);
@@ -523,7 +526,8 @@ static hipError_t gemm_splitk(int M, int N, int K, double alpha, const T* A, int
 }
 
 template <class T, int MIXED>
-static hipError_t lg_factor(T* W, int64_t n, double* dacc, T* rinv, int32_t* info, hipStream_t s)
+static hipError_t lg_factor(T* W, int64_t n, double* dacc, T* rinv, T* part, int64_t part_cap,
+                            int32_t* info, hipStream_t s)
 {
     constexpr int NB = LG_NB<T>;
     const size_t smem = lg_diag_smem<T>();
@@ -541,9 +545,12 @@ static hipError_t lg_factor(T* W, int64_t n, double* dacc, T* rinv, int32_t* inf
         hipLaunchKernelGGL((k_lg_diag_factor<T, MIXED>), dim3(1), dim3(NB * LG_TPC), smem, s, W, n, (int)r0,
                            nl, dacc, rv, info);
         if (mr <= 0) break;
-        // R_I,>I = R_II^{-T} A_I,>I  (in place: one M tile spans the panel)
-        hipError_t e = gemm<T, T, T>(nl, (int)mr, nl, 1.0, rv, NB, 1, W + r0 * n + c0, n, 0, 0.0,
-                                     W + r0 * n + c0, n, 0, s);
+        // R_I,>I = R_II^{-T} A_I,>I over one tile row: K split (32 deep) so that
+        // the GPU fills; the partials are reduced into place after every split
+        // has read A_I,>I (without a split, one M tile spans the panel, so the
+        // product is also safe in place)
+        hipError_t e = gemm_splitk<T>(nl, (int)mr, nl, 1.0, rv, NB, 1, W + r0 * n + c0, n, 0,
+                                      W + r0 * n + c0, n, part, part_cap, s, 0, 32);
         if (e != hipSuccess) return e;
         if (MIXED)
             hipLaunchKernelGGL(k_lg_dacc<T>, dim3(blocks_for(mr, 64)), dim3(64), 0, s, W, n, (int)r0,
@@ -683,7 +690,7 @@ static hipError_t lg_inverse(int64_t n, const T* a, int64_t lda, T* x, int64_t l
     if (MIXED)
         hipLaunchKernelGGL(k_lg_dacc_init<T>, dim3(blocks_for(n)), dim3(256), 0, s, a, lda, (int)n,
                            dacc);
-    hipError_t e = lg_factor<T, MIXED>(W, n, dacc, rinv, info, s);
+    hipError_t e = lg_factor<T, MIXED>(W, n, dacc, rinv, part, L.part_elems, info, s);
     if (e != hipSuccess) return e;
     if (lg_use_blocked_iv()) {
         e = lg_inverse_from_r<T>(W, n, rinv, x, ldx, ctmp, wblk, part, L.part_elems, s);
@@ -741,14 +748,16 @@ hipError_t large_factor(int dtype, int64_t n, void* a, int64_t lda, int32_t* inf
         LgWork<float> L(n, 0);
         char* w = static_cast<char*>(work);
         return lg_factor<float, 0>(static_cast<float*>(a), n, reinterpret_cast<double*>(w + L.dacc),
-                                   reinterpret_cast<float*>(w + L.rinv), info, s);
+                                   reinterpret_cast<float*>(w + L.rinv),
+                                   reinterpret_cast<float*>(w + L.part), L.part_elems, info, s);
     }
     if (dtype == DT_F64) {
         LgWork<double> L(n, 0);
         char* w = static_cast<char*>(work);
         return lg_factor<double, 0>(static_cast<double*>(a), n,
                                     reinterpret_cast<double*>(w + L.dacc),
-                                    reinterpret_cast<double*>(w + L.rinv), info, s);
+                                    reinterpret_cast<double*>(w + L.rinv),
+                                    reinterpret_cast<double*>(w + L.part), L.part_elems, info, s);
     }
     return hipErrorNotSupported;
 }
