@@ -166,8 +166,11 @@ __device__ __forceinline__ void gemm_tile(int bid, int nblocks, int ntiles, int 
     bn = r + rem;
 }
 
+// Two workgroups per CU (two waves per SIMD): the LDS of two fits, and the
+// FP64 accumulators alone take 128 registers, so the register budget must
+// be bounded for the second workgroup to be resident.
 template <class T, class TA, class TB, bool AKC, bool BKC>
-__global__ void __launch_bounds__(G_THREADS)
+__global__ void __launch_bounds__(G_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
 k_gemm(GemmArgs p)
 {
     using Acc = typename mfma_acc<T>::type;
