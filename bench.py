@@ -208,6 +208,27 @@ def plain_small_workload(torch, api, G, O, dev, steps):
             "plain_c128_4x4_max_rel_err": float(err.max())}
 
 
+def solve_workload(torch, api, mats, steps):
+    """Batched solves with one right-hand side per system from the factors of
+    the MIMO batches (eqs. 5-7): time of the solve launch alone and of factor +
+    solve.  Algorithmic bytes per system: the upper triangle of R, y and x."""
+    out = {}
+    g = torch.Generator(device=mats[0].device).manual_seed(3)
+    for A in mats:
+        count, n = A.shape[0], A.shape[-1]
+        Rf = api.factor(A)
+        Y = torch.randn((count, n), dtype=A.dtype, device=A.device, generator=g)
+        X = torch.empty_like(Y)
+        ms, (ls,) = _time_loop(torch, [lambda: api.solve_factored(Rf, Y, out=X)], steps, 2)
+        fs_ms, _ = _time_loop(torch, [lambda: api.solve(A, Y)], max(2, steps // 2), 1)
+        per_sys = (n * (n + 1) // 2 + 2 * n) * A.element_size()
+        key = "solve_c64_%dx%d" % (n, n)
+        out[key + "_per_s"] = count / (ls / 1e3)
+        out[key + "_hbm_frac"] = count * per_sys / (ls / 1e3) / HBM_PEAK
+        out[key + "_factor_plus_solve_per_s"] = count / (fs_ms / 1e3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -361,6 +382,8 @@ def main():
         details["grad16_max_rel_err"] = float(gerr.max())
         del AG, GG, XG
 
+    if not args.no_extras:
+        details.update(solve_workload(torch, api, [A8, A16], max(3, args.steps // 2)))
     if not args.no_extras and not args.no_large:
         details.update(large_workloads(torch, api, G, dev, max(2, args.steps // 4)))
     if not args.no_extras:

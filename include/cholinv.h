@@ -119,6 +119,37 @@ int ldl_factor(int dtype, int64_t batch, int64_t n, void* a, int64_t lda, int64_
                void* d, int32_t* info, void* stream);
 
 /*
+ * chol_solve -- X_b = A_b^{-1} Y_b for a batch of small systems, from the
+ * factor written by chol_factor (Cholesky: R^* b = y then R x = b, Section II
+ * eqs. 5-7) or ldl_factor (LDL: R^* c = y, b_i = c_i/d_i, R x = b, Section
+ * II.A eqs. 12-14); 2 x n^2/2 multiplies per right-hand side.
+ *   dtype      CI_F32 / CI_F64 / CI_C64 / CI_C128
+ *   method     CI_METHOD_CHOL or CI_METHOD_LDL
+ *   batch      number of systems (>= 0)
+ *   n          order, 0 <= n <= CI_SMALL_NMAX
+ *   nrhs       right-hand sides per system (>= 0)
+ *   r, ldr, stride_r  device, the factors: the upper triangle of matrix b at
+ *              r + b*stride_r holds R (CHOL: with its real positive diagonal;
+ *              LDL: the strict upper part of the unit R, whose diagonal is
+ *              implied).  Nothing below the diagonal is read.
+ *   d          device, LDL pivots as ldl_factor wrote them (float for
+ *              CI_F32/CI_C64, double otherwise; matrix b's at d + b*n);
+ *              ignored for CHOL (may be NULL)
+ *   b, ldb, stride_b  device, right-hand sides: an n x nrhs row-major block
+ *              per system, element (i, c) of system b at b + b*stride_b +
+ *              i*ldb + c; column c is one right-hand side
+ *   x, ldx, stride_x  device, solutions in the same layout; x may equal b
+ *              (in place) when ldx == ldb and stride_x == stride_b, and must
+ *              not overlap it otherwise
+ * Strides are ignored when batch == 1.  A zero or non-finite pivot gives
+ * non-finite solutions (the factorisation's info reports it); no info is
+ * written here.  Precision: the element type throughout.
+ */
+int chol_solve(int dtype, int method, int64_t batch, int64_t n, int64_t nrhs, const void* r,
+               int64_t ldr, int64_t stride_r, const void* d, const void* b, int64_t ldb,
+               int64_t stride_b, void* x, int64_t ldx, int64_t stride_x, void* stream);
+
+/*
  * chol_inverse -- X = A^{-1} of one matrix of any order by the proposed method
  * (Section IV): factorisation, then one back-substitution R X = S against the
  * known upper triangle S = diag(1/r_ii) (eq. 24) or diag(1/d_i) (eq. 29) of

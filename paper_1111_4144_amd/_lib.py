@@ -22,7 +22,7 @@ CI_ERR_LAUNCH = -1000
 CI_SMALL_NMAX = 64
 
 # Every symbol include/cholinv.h declares.
-EXPORTS = ("chol_factor", "ldl_factor", "chol_inverse", "chol_inverse_batched",
+EXPORTS = ("chol_factor", "ldl_factor", "chol_solve", "chol_inverse", "chol_inverse_batched",
            "chol_inverse_backward", "chol_workspace_size", "chol_status_string", "chol_version",
            "chol_autotune", "chol_tuned_engine", "chol_autotune_clear")
 
@@ -56,6 +56,8 @@ def lib():
     L = ctypes.CDLL(LIB_PATH)
     L.chol_factor.argtypes = [_i32, _i64, _i64, _vp, _i64, _i64, _vp, _vp, _sz, _vp]
     L.ldl_factor.argtypes = [_i32, _i64, _i64, _vp, _i64, _i64, _vp, _vp, _vp]
+    L.chol_solve.argtypes = [_i32, _i32, _i64, _i64, _i64, _vp, _i64, _i64, _vp, _vp, _i64, _i64,
+                             _vp, _i64, _i64, _vp]
     L.chol_inverse.argtypes = [_i32, _i64, _vp, _i64, _vp, _i64, ctypes.POINTER(ci_opts), _vp,
                                _sz, _vp, _vp]
     L.chol_inverse_batched.argtypes = [_i32, _i64, _i64, _vp, _vp, _i64, _vp, _i64, _vp, _i64,
@@ -70,7 +72,7 @@ def lib():
     L.chol_tuned_engine.argtypes = [_i32, ctypes.POINTER(ci_opts), _i32]
     L.chol_autotune_clear.argtypes = []
     L.chol_autotune_clear.restype = None
-    for fn in ("chol_factor", "ldl_factor", "chol_inverse", "chol_inverse_batched",
+    for fn in ("chol_factor", "ldl_factor", "chol_solve", "chol_inverse", "chol_inverse_batched",
                "chol_inverse_backward"):
         getattr(L, fn).restype = _i32
     _lib = L

@@ -188,6 +188,64 @@ def ldl(A: torch.Tensor, *, return_info=False):
     return (R, d, info.reshape(A.shape[:-2])) if return_info else (R, d)
 
 
+def _rhs_block(Y, n, lead):
+    """(Y as [B, n, k], vector?) for right-hand sides [..., n] or [..., n, k]."""
+    if Y.dim() == lead + 1 and Y.shape[-1] == n:
+        return Y.reshape(-1, n, 1), True
+    if Y.dim() == lead + 2 and Y.shape[-2] == n:
+        return Y.reshape(-1, n, Y.shape[-1]), False
+    raise ValueError("right-hand sides must be [..., n] or [..., n, k] with the factor's batch")
+
+
+def solve_factored(R: torch.Tensor, Y: torch.Tensor, *, d: torch.Tensor | None = None,
+                   out: torch.Tensor | None = None) -> torch.Tensor:
+    """x = A^{-1} y from the factor of A: R from :func:`factor` (eqs. 5-7) or,
+    with d, (R, d) from :func:`ldl` (eqs. 12-14).  Y is [..., n] (one
+    right-hand side per matrix) or [..., n, k]; out may be Y (in place)."""
+    _check_device(R, Y)
+    if Y.dtype != R.dtype:
+        raise TypeError("Y must have the factor's dtype")
+    n = R.shape[-1]
+    lead = R.dim() - 2
+    R3 = R.reshape(-1, n, n).contiguous()
+    B = R3.shape[0]
+    Y3, vec = _rhs_block(Y.contiguous(), n, lead)
+    if Y3.shape[0] != B:
+        raise ValueError("batch of Y does not match the factor's")
+    k = Y3.shape[-1]
+    if out is None:
+        X = torch.empty(Y.shape, dtype=Y.dtype, device=Y.device)
+    elif out.shape != Y.shape or out.dtype != Y.dtype or not out.is_contiguous():
+        raise ValueError("out must be a contiguous tensor shaped like Y")
+    else:
+        X = out
+    X3 = X.view(Y3.shape)
+    method = L.CI_METHOD_CHOL
+    if d is not None:
+        method = L.CI_METHOD_LDL
+        d = d.reshape(B, n).contiguous()
+        _check_device(d)
+    rc = L.lib().chol_solve(_dtype_code(R), method, B, n, k, _ptr(R3), n, n * n,
+                            None if d is None else _ptr(d), _ptr(Y3), k, n * k, _ptr(X3), k,
+                            n * k, _stream(R.device))
+    L.check("chol_solve", rc)
+    return X
+
+
+def solve(A: torch.Tensor, Y: torch.Tensor, *, method="chol", return_info=False):
+    """x = A^{-1} y for Hermitian positive-definite A[..., n, n] (n <= 64):
+    the factorisation (eqs. 3-4 or 10-11), then the two substitutions."""
+    if method == "chol":
+        Rf, info = factor(A, return_info=True)
+        X = solve_factored(Rf, Y)
+    elif method == "ldl":
+        Rf, d, info = ldl(A, return_info=True)
+        X = solve_factored(Rf, Y, d=d)
+    else:
+        raise ValueError("method must be 'chol' or 'ldl'")
+    return (X, info) if return_info else X
+
+
 _DT_CODE = {"f32": L.CI_F32, "f64": L.CI_F64, "c64": L.CI_C64, "c128": L.CI_C128}
 
 

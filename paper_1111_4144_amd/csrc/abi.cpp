@@ -103,6 +103,36 @@ int ldl_factor(int dtype, int64_t batch, int64_t n, void* a, int64_t lda, int64_
     return map_err(run_small(dtype, n, ci::OP_LDL_FACTOR, 1, 0, p, s));
 }
 
+int chol_solve(int dtype, int method, int64_t batch, int64_t n, int64_t nrhs, const void* r,
+               int64_t ldr, int64_t stride_r, const void* d, const void* b, int64_t ldb,
+               int64_t stride_b, void* x, int64_t ldx, int64_t stride_x, void* stream)
+{
+    if (!valid_dtype(dtype)) return -1;
+    if (method != CI_METHOD_CHOL && method != CI_METHOD_LDL) return -2;
+    if (batch < 0) return -3;
+    if (n < 0 || n > CI_SMALL_NMAX) return -4;
+    if (nrhs < 0 || nrhs > INT32_MAX) return -5;
+    const bool work = batch > 0 && n > 0 && nrhs > 0;
+    if (work && !r) return -6;
+    if (ldr < std::max<int64_t>(1, n)) return -7;
+    if (batch > 1 && stride_r < ldr * n) return -8;
+    if (work && method == CI_METHOD_LDL && !d) return -9;
+    if (work && !b) return -10;
+    if (ldb < std::max<int64_t>(1, nrhs)) return -11;
+    if (batch > 1 && stride_b < ldb * n) return -12;
+    if (work && !x) return -13;
+    if (ldx < std::max<int64_t>(1, nrhs)) return -14;
+    if (batch > 1 && stride_x < ldx * n) return -15;
+    if (x == b && (ldx != ldb || (batch > 1 && stride_x != stride_b))) return -13;
+    if (!work) return 0;
+    // one lane per right-hand side; the grid (32-lane blocks at the least)
+    // must stay below 2^32 blocks
+    if (batch > ((int64_t)1 << 36) / nrhs) return -5;
+    ci::SolveArgs p{r, ldr, batch > 1 ? stride_r : 0, d, b, ldb, batch > 1 ? stride_b : 0,
+                    x, ldx, batch > 1 ? stride_x : 0, batch, (int)n, (int)nrhs};
+    return map_err(ci::launch_solve(dtype, method, p, (hipStream_t)stream));
+}
+
 int chol_inverse(int dtype, int64_t n, const void* a, int64_t lda, void* x, int64_t ldx,
                  const ci_opts* opts, void* work, size_t work_bytes, int32_t* info, void* stream)
 {

@@ -94,6 +94,22 @@ hipError_t launch_wpm_f64(int n, int op, int method, int mixed, const BatchArgs&
 hipError_t launch_wpm_c64(int n, int op, int method, int mixed, const BatchArgs& p, hipStream_t s);
 hipError_t launch_wpm_c128(int n, int op, int method, int mixed, const BatchArgs& p, hipStream_t s);
 
+// Solves A x = y with the factor of A (orders <= 64): one lane per
+// right-hand side.  Right-hand sides are the columns of an n x nrhs row-major
+// block per matrix; d holds the LDL pivots (real type of V, n per matrix).
+struct SolveArgs {
+    const void* r;
+    int64_t ldr, sr;
+    const void* d;
+    const void* b;
+    int64_t ldb, sb;
+    void* x;
+    int64_t ldx, sx;
+    int64_t batch;
+    int n, nrhs;
+};
+hipError_t launch_solve(int dtype, int method, const SolveArgs& p, hipStream_t s);
+
 // Backward gA = -X Gh X.
 hipError_t launch_backward(int dtype, int n, const void* x, const void* g, void* ga,
                            int64_t batch, int64_t stride, hipStream_t s);

@@ -1,4 +1,4 @@
-// wpm_c64.hip -- LDS-resident group kernels (orders 17..32) for cf elements.
+// wpm_c64.hip -- LDS-resident group kernels (orders 17..64) for cf elements.
 #include "wpm_impl.hpp"
 
 namespace ci {
@@ -7,6 +7,7 @@ hipError_t launch_wpm_c64(int n, int op, int method, int mixed, const BatchArgs&
                             hipStream_t s)
 {
     if (n <= 32) return wpm_run_ops<cf, 32>(n, op, method, mixed, p, s);
+    if (n <= 64) return wpm_run_ops<cf, 64>(n, op, method, mixed, p, s);
     return hipErrorNotSupported;
 }
 

@@ -70,6 +70,15 @@ def test_argument_validation_codes():
     assert lib.ldl_factor(0, 2, 4, p, 4, 16, None, None, None) == -7
     # backward: order too large
     assert lib.chol_inverse_backward(2, 1, 65, p, p, p, 65 * 65, None) == -3
+    # solve: bad method, order beyond the batched limit, LDL without d,
+    # ldb < nrhs, stride_b too small, in place with a different layout
+    assert lib.chol_solve(0, 2, 1, 4, 1, p, 4, 16, None, p, 1, 4, p, 1, 4, None) == -2
+    assert lib.chol_solve(0, 0, 1, 65, 1, p, 65, 0, None, p, 1, 65, p, 1, 65, None) == -4
+    assert lib.chol_solve(0, 1, 2, 4, 1, p, 4, 16, None, p, 1, 4, p, 1, 4, None) == -9
+    assert lib.chol_solve(0, 0, 2, 4, 3, p, 4, 16, None, p, 2, 12, p, 3, 12, None) == -11
+    assert lib.chol_solve(0, 0, 2, 4, 2, p, 4, 16, None, p, 2, 7, p, 2, 8, None) == -12
+    assert lib.chol_solve(0, 0, 2, 4, 2, p, 4, 16, None, p, 2, 8, p, 2, 9, None) == -13
+    assert lib.chol_solve(0, 0, 0, 4, 1, None, 4, 16, None, None, 1, 4, None, 1, 4, None) == 0
     # empty work is a no-op
     assert lib.chol_inverse_batched(2, 0, 4, None, None, 0, None, 16, None, 16, None, None, 0,
                                     None, None) == 0

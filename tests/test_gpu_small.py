@@ -71,14 +71,14 @@ def test_real_small(n, dtype, method):
         print("%s n=%d %s %s ns=%d: max rel err %.3e, max err/kappa %.3e" % (dtype, n, method, prec, ns, e, r))
 
 
-@pytest.mark.parametrize("n", [9, 12, 16, 17, 24, 32])
+@pytest.mark.parametrize("n", [9, 12, 16, 17, 24, 32, 33, 48, 64])
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
 @pytest.mark.parametrize("method", ["chol", "ldl"])
 def test_complex_group(n, dtype, method):
     """Complex orders beyond the thread-per-matrix range (lane groups / LDS)."""
     t = torch_cuda()
     npd = np.complex64 if dtype == "c64" else np.complex128
-    a = G.mimo(n, 300, seed=11 + n).astype(npd)
+    a = G.mimo(n, 300 if n <= 32 else 97, seed=11 + n).astype(npd)
     precs = [("plain", 0)] + ([("mixed", 1)] if dtype == "c64" else [])
     xo, io = O.inv_prop(a, method)
     for prec, ns in precs:
@@ -195,21 +195,26 @@ def test_staged_and_direct_variants_agree():
     assert t.equal(x_dense, x_direct)
 
 
-def test_factorisations_match_oracle():
+@pytest.mark.parametrize("n", [7, 40])
+def test_factorisations_match_oracle(n):
     t = torch_cuda()
     from paper_1111_4144_amd import api
-    a = G.mimo(7, 200, seed=8).astype(np.complex128)
+    a = G.mimo(n, 200, seed=8).astype(np.complex128)
     r = api.factor(_gpu(t, a)).cpu().numpy()
     rl, d = api.ldl(_gpu(t, a))
     rl, d = rl.cpu().numpy(), d.cpu().numpy()
-    il = np.tril_indices(7, -1)
+    il = np.tril_indices(n, -1)
     for b in (0, 99, 199):
         ro, _ = O.chol(a[b])
         rlo, do, _ = O.ldl(a[b])
-        assert np.allclose(np.triu(r[b]), ro, rtol=1e-12, atol=1e-13)
+        # FP64 factors: entrywise at order 7; at order 40 (condition numbers up
+        # to ~1e4) relative to the largest entry
+        at = 1e-13 if n <= 8 else 1e-11 * np.abs(ro).max()
+        atl = 1e-13 if n <= 8 else 1e-11 * np.abs(rlo).max()
+        assert np.allclose(np.triu(r[b]), ro, rtol=1e-12, atol=at)
         assert np.array_equal(r[b][il], a[b][il])          # strict lower untouched
-        assert np.allclose(np.triu(rl[b], 1), np.triu(rlo, 1), rtol=1e-12, atol=1e-13)
-        assert np.allclose(d[b], do, rtol=1e-12)
+        assert np.allclose(np.triu(rl[b], 1), np.triu(rlo, 1), rtol=1e-12, atol=atl)
+        assert np.allclose(d[b], do, rtol=1e-12 if n <= 8 else 1e-10)
         assert np.array_equal(np.diag(rl[b]), np.diag(a[b]))
 
 
