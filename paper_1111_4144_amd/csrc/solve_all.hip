@@ -9,12 +9,15 @@
 // the vector in registers (loops unrolled to a compile-time bound, the order
 // itself a runtime value); orders 17..64 keep it in LDS, one column per lane
 // at a lane-interleaved address so a wave's accesses fall in distinct banks.
-// The factor is read from global memory: every lane of a wave reads the same
-// (i, k) entry of its own matrix at the same time, so each matrix's cache
-// lines are fetched once and then hit.
+// Dense batches with one right-hand side (the factors back to back, each
+// vector contiguous) take the staged kernel: a block of 64 lanes copies its 64
+// factors into LDS with 16-byte loads (upper triangles kept, packed), loads
+// each vector with wide loads, and each lane substitutes from its LDS slot.
+// Other layouts read the factor from global memory entry by entry.
 #include "ci_launch.hpp"
 #include "ci_types.hpp"
 #include "cholinv.h"
+#include "tpm_impl.hpp"
 
 namespace ci {
 
@@ -113,10 +116,92 @@ __global__ void __launch_bounds__(LDS_LANES<V>) k_solve_lds(SolveArgs p)
     for (int i = 0; i < n; ++i) x[(int64_t)i * p.ldx] = y[i * L];
 }
 
+// Exact order N, one right-hand side, dense: factor from its packed LDS slot.
+template <class V, int METHOD, int N>
+__global__ void __launch_bounds__(TPM_BLOCK) k_solve_staged(SolveArgs p)
+{
+    using R = typename vt<V>::real;
+    constexpr int SL = Slot<N, true>::SIZE;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    V* sm = reinterpret_cast<V*>(smem_raw);
+    const int t = threadIdx.x;
+    const int64_t b0 = (int64_t)blockIdx.x * TPM_BLOCK;
+    const int nvalid = (int)((p.batch - b0) < TPM_BLOCK ? (p.batch - b0) : TPM_BLOCK);
+    stage_in<V, N, true>((const V*)p.r, sm, b0, nvalid, t);
+    __syncthreads();
+    if (t >= nvalid) return;
+    const int64_t m = b0 + t;
+    const V* slot = sm + t * SL;
+    V y[N];
+    load_vec<V, N>((const V*)p.b + m * N, y);
+    R inv[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        V acc = y[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) msubc(acc, slot[pidx<N>(k, i)], y[k]);
+        if constexpr (METHOD == 0) {
+            inv[i] = R(1) / re(slot[pidx<N>(i, i)]);
+            y[i] = scal(acc, inv[i]);
+        } else {
+            inv[i] = R(1) / ((const R*)p.d)[m * N + i];
+            y[i] = acc;
+        }
+    }
+#pragma unroll
+    for (int i = N - 1; i >= 0; --i) {
+        V acc = (METHOD == 0) ? y[i] : scal(y[i], inv[i]);
+#pragma unroll
+        for (int k = i + 1; k < N; ++k) msub(acc, slot[pidx<N>(i, k)], y[k]);
+        y[i] = (METHOD == 0) ? scal(acc, inv[i]) : acc;
+    }
+    store_vec<V, N>((V*)p.x + m * N, y);
+}
+
+template <class V, int METHOD, int N>
+hipError_t solve_staged(const SolveArgs& p, hipStream_t s)
+{
+    const size_t smem = (size_t)TPM_BLOCK * Slot<N, true>::SIZE * sizeof(V);
+    auto kern = k_solve_staged<V, METHOD, N>;
+    if (smem > 65536) {
+        static bool once = false;
+        if (!once) {
+            hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)smem);
+            if (e != hipSuccess) return e;
+            once = true;
+        }
+    }
+    const int64_t blocks = (p.batch + TPM_BLOCK - 1) / TPM_BLOCK;
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(TPM_BLOCK), smem, s, p);
+    return hipGetLastError();
+}
+
+// The staged kernel needs whole factors back to back, contiguous vectors and
+// 16-byte aligned bases (its wide accesses).
+bool staged_layout(const SolveArgs& p, size_t es)
+{
+    const int64_t n = p.n;
+    const bool dense = p.nrhs == 1 && p.ldr == n && (p.batch == 1 || p.sr == n * n) &&
+                       p.ldb == 1 && p.ldx == 1 && (p.batch == 1 || (p.sb == n && p.sx == n));
+    const auto al = [](const void* q) { return ((uintptr_t)q & 15) == 0; };
+    return dense && al(p.r) && al(p.b) && al(p.x) && (n * es) % 16 == 0;
+}
+
 template <class V, int METHOD>
 hipError_t solve_method(const SolveArgs& p, hipStream_t s)
 {
     const int64_t lanes = p.batch * p.nrhs;
+    if (staged_layout(p, sizeof(V))) {
+        switch (p.n) {
+        case 2: return solve_staged<V, METHOD, 2>(p, s);
+        case 4: return solve_staged<V, METHOD, 4>(p, s);
+        case 8: return solve_staged<V, METHOD, 8>(p, s);
+        case 16: return solve_staged<V, METHOD, 16>(p, s);
+        default: break;
+        }
+    }
     if (p.n > 16) {
         constexpr int L = LDS_LANES<V>;
         hipLaunchKernelGGL((k_solve_lds<V, METHOD>), dim3((unsigned)((lanes + L - 1) / L)),

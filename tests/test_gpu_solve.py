@@ -56,7 +56,8 @@ def _oracle_solve(a, y, method):
 
 @pytest.mark.parametrize("method", ["chol", "ldl"])
 @pytest.mark.parametrize("dt", ["f32", "f64", "c64", "c128"])
-@pytest.mark.parametrize("n,k", [(1, 1), (7, 1), (16, 3), (24, 1), (64, 2)])
+@pytest.mark.parametrize("n,k", [(1, 1), (2, 1), (4, 1), (7, 1), (8, 1), (16, 1), (16, 3),
+                                 (24, 1), (64, 2)])
 def test_solve_vs_oracle(n, k, dt, method):
     t = torch_cuda()
     from paper_1111_4144_amd import api
@@ -134,6 +135,13 @@ def test_solve_in_place_and_strided():
     xs = X.cpu().numpy().reshape(batch, n + 1, ldb)
     assert_within(xs[:, :n, :k], ref, a, TOL_FP64, "strided")
     assert (xs[:, :n, k:] == -3.5).all() and (xs[:, n, :] == -3.5).all()
+    # in place with one right-hand side per system (the LDS-staged kernel)
+    a8, y8 = _inputs("c64", 130, 8, 1, 37)
+    ref8 = _oracle_solve(a8, y8, "chol")
+    R8 = api.factor(t.from_numpy(a8).cuda())
+    Y8 = t.from_numpy(y8[:, :, 0].copy()).cuda()
+    assert api.solve_factored(R8, Y8, out=Y8).data_ptr() == Y8.data_ptr()
+    assert_within(Y8.cpu().numpy()[:, :, None], ref8, a8, TOL_FP32, "in place, staged")
     # empty batch / empty order / no right-hand sides: nothing to do
     lib = L.lib()
     assert lib.chol_solve(L.CI_F64, 0, 0, n, k, None, n, 0, None, None, k, 0, None, k, 0, None) == 0
