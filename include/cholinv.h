@@ -203,6 +203,29 @@ int chol_inverse_batched(int dtype, int64_t batch, int64_t n_uniform, const int3
                          void* work, size_t work_bytes, int32_t* info, void* stream);
 
 /*
+ * chol_inverse_nonherm -- D_b^{-1} for a batch of general (not Hermitian)
+ * nonsingular square matrices by the route of Section III.C: A = D D^* is
+ * Hermitian positive definite, so D^{-1} = D^* A^{-1}.  Three steps on
+ * `stream`: A = D D^* (upper triangle) into the workspace, X_A = A^{-1} by
+ * the batched Section IV inversion (opts: method, precision, ns_steps;
+ * fill_lower is ignored), then D^{-1} = D^* X_A into x.  The condition number
+ * of A is the square of that of D, so the accuracy is that of an inversion
+ * at kappa(D)^2.
+ *   batch      number of matrices, <= 2^28
+ *   n          order, 0 <= n <= CI_SMALL_NMAX
+ *   d, stride  device input, matrix b at d + b*stride, leading dimension n
+ *              (stride >= n*n; ignored when batch == 1); not modified
+ *   x          device output, same layout as d; must not overlap d
+ *   work       device scratch of work_bytes >= chol_workspace_size(
+ *              CI_FN_NONHERM, dtype, batch, n, opts) (two dense batches)
+ *   info       device int32[batch] or NULL: the first failing pivot of the
+ *              factorisation of D D^* (a singular D), whose output is NaN
+ */
+int chol_inverse_nonherm(int dtype, int64_t batch, int64_t n, const void* d, int64_t stride,
+                         void* x, const ci_opts* opts, void* work, size_t work_bytes,
+                         int32_t* info, void* stream);
+
+/*
  * chol_inverse_backward -- adjoint of X = A^{-1} for the real loss
  * L = Re<G, X> restricted to Hermitian A:  gA = -X Gh X, Gh = (G + G^H)/2.
  * It reuses the forward's X (full Hermitian, e.g. written with fill_lower = 1)
@@ -214,7 +237,7 @@ int chol_inverse_backward(int dtype, int64_t batch, int64_t n, const void* x, co
                           void* ga, int64_t stride, void* stream);
 
 /* Which entry point a workspace query is for. */
-enum { CI_FN_FACTOR = 0, CI_FN_INVERSE = 1, CI_FN_BATCHED = 2 };
+enum { CI_FN_FACTOR = 0, CI_FN_INVERSE = 1, CI_FN_BATCHED = 2, CI_FN_NONHERM = 3 };
 
 /* Bytes of device scratch the named entry point needs for these arguments
  * (0 when none).  For CI_FN_BATCHED pass n = n_uniform (0 for varlen). */

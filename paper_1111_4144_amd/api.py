@@ -246,6 +246,32 @@ def solve(A: torch.Tensor, Y: torch.Tensor, *, method="chol", return_info=False)
     return (X, info) if return_info else X
 
 
+def inverse_nonherm(D: torch.Tensor, *, method="chol", precision="plain", ns_steps=None,
+                    return_info=False, check_errors=False):
+    """D^{-1} for general nonsingular D[..., n, n] (n <= 64) by Section III.C:
+    A = D D^* is Hermitian positive definite and D^{-1} = D^* A^{-1}.  The
+    options apply to the inversion of A (whose condition number is kappa(D)^2)."""
+    _check_device(D)
+    n = D.shape[-1]
+    D3 = D.reshape(-1, n, n).contiguous()
+    B = D3.shape[0]
+    X = torch.empty_like(D3)
+    info = torch.zeros(B, dtype=torch.int32, device=D.device)
+    lib = L.lib()
+    dt = _dtype_code(D)
+    if ns_steps is None:
+        ns_steps = 1 if precision == "mixed" else 0
+    opts = L.make_opts(method, precision, ns_steps)
+    ws = lib.chol_workspace_size(L.CI_FN_NONHERM, dt, B, n, ctypes.byref(opts))
+    work = _workspace(ws, D.device)
+    rc = lib.chol_inverse_nonherm(dt, B, n, _ptr(D3), n * n, _ptr(X), ctypes.byref(opts),
+                                  _ptr(work), ws, _ptr(info), _stream(D.device))
+    L.check("chol_inverse_nonherm", rc)
+    _finish("inverse_nonherm", info, check_errors)
+    X = X.reshape(D.shape)
+    return (X, info.reshape(D.shape[:-2])) if return_info else X
+
+
 _DT_CODE = {"f32": L.CI_F32, "f64": L.CI_F64, "c64": L.CI_C64, "c128": L.CI_C128}
 
 

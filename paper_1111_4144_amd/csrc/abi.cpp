@@ -7,6 +7,7 @@
 
 #include "ci_launch.hpp"
 #include "ci_large.hpp"
+#include "ci_nonherm.hpp"
 #include "cholinv.h"
 
 namespace {
@@ -133,6 +134,36 @@ int chol_solve(int dtype, int method, int64_t batch, int64_t n, int64_t nrhs, co
     return map_err(ci::launch_solve(dtype, method, p, (hipStream_t)stream));
 }
 
+int chol_inverse_nonherm(int dtype, int64_t batch, int64_t n, const void* d, int64_t stride,
+                         void* x, const ci_opts* opts, void* work, size_t work_bytes,
+                         int32_t* info, void* stream)
+{
+    if (!valid_dtype(dtype)) return -1;
+    if (batch < 0 || batch > ((int64_t)1 << 28)) return -2;
+    if (n < 0 || n > CI_SMALL_NMAX) return -3;
+    if (batch > 0 && n > 0 && !d) return -4;
+    if (batch > 1 && stride < n * n) return -5;
+    if (batch > 0 && n > 0 && (!x || x == d)) return -6;
+    ci_opts o = opts ? *opts : default_opts();
+    if (check_opts(o, dtype)) return -7;
+    hipStream_t s = (hipStream_t)stream;
+    if (batch == 0) return 0;
+    if (n == 0) return info ? map_err(ci::fill_i32(info, batch, 0, s)) : 0;
+    const size_t need = chol_workspace_size(CI_FN_NONHERM, dtype, batch, n, &o);
+    if (work_bytes < need || !work) return CI_ERR_WORKSPACE;
+    const int64_t nn = n * n;
+    const int64_t sd = batch > 1 ? stride : nn;
+    void* a = work;
+    void* xa = (char*)work + need / 2;
+    hipError_t e = ci::launch_gram(dtype, d, sd, a, batch, (int)n, s);
+    if (e != hipSuccess) return map_err(e);
+    // X_A = (D D^*)^{-1}, written in full (both halves feed the product)
+    ci::BatchArgs p{a, xa, batch, n, nn, n, nn, o.ns_steps, 1, info, nullptr};
+    e = run_small(dtype, n, ci::OP_INV, o.method, o.precision == CI_MIXED, p, s);
+    if (e != hipSuccess) return map_err(e);
+    return map_err(ci::launch_adjoint_product(dtype, d, sd, xa, x, sd, batch, (int)n, s));
+}
+
 int chol_inverse(int dtype, int64_t n, const void* a, int64_t lda, void* x, int64_t ldx,
                  const ci_opts* opts, void* work, size_t work_bytes, int32_t* info, void* stream)
 {
@@ -220,6 +251,11 @@ size_t chol_workspace_size(int fn, int dtype, int64_t batch, int64_t n, const ci
                    : 0;
     case CI_FN_BATCHED:
         return n == 0 ? ci::varlen_workspace(batch) : 0;
+    case CI_FN_NONHERM: {
+        // two dense batches (D D^* and its inverse), each rounded to 256 bytes
+        const size_t one = ((size_t)batch * n * n * elem_size(dtype) + 255) / 256 * 256;
+        return n > CI_SMALL_NMAX ? 0 : 2 * one;
+    }
     default:
         return 0;
     }

@@ -79,6 +79,14 @@ def test_argument_validation_codes():
     assert lib.chol_solve(0, 0, 2, 4, 2, p, 4, 16, None, p, 2, 7, p, 2, 8, None) == -12
     assert lib.chol_solve(0, 0, 2, 4, 2, p, 4, 16, None, p, 2, 8, p, 2, 9, None) == -13
     assert lib.chol_solve(0, 0, 0, 4, 1, None, 4, 16, None, None, 1, 4, None, 1, 4, None) == 0
+    # non-Hermitian inverse: order beyond the batched limit, output = input,
+    # workspace too small (two dense batches are needed)
+    assert lib.chol_inverse_nonherm(0, 2, 65, p, 65 * 65, p, None, None, 0, None, None) == -3
+    assert lib.chol_inverse_nonherm(0, 2, 4, p, 16, p, None, None, 0, None, None) == -6
+    q = ctypes.c_void_p(0x2000)
+    assert lib.chol_inverse_nonherm(0, 2, 4, p, 16, q, None, p, 255, None, None) == \
+        L.CI_ERR_WORKSPACE
+    assert lib.chol_workspace_size(L.CI_FN_NONHERM, 0, 2, 4, None) == 512
     # empty work is a no-op
     assert lib.chol_inverse_batched(2, 0, 4, None, None, 0, None, 16, None, 16, None, None, 0,
                                     None, None) == 0
