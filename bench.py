@@ -229,6 +229,26 @@ def solve_workload(torch, api, mats, steps):
     return out
 
 
+def nonherm_workload(torch, api, dev, steps):
+    """General (non-Hermitian) complex64 8 x 8 inverses through D D^* (Section
+    III.C), 524,288 per batch, mixed precision with one refinement step; the
+    left-inverse residual max |X D - I| over the batch."""
+    n, count = 8, 1 << 19
+    g = torch.Generator(device=dev).manual_seed(5)
+    D = torch.randn((count, n, n), dtype=torch.complex64, device=dev, generator=g)
+    D += (n ** 0.5) * torch.eye(n, dtype=torch.complex64, device=dev)
+    state = {}
+
+    def f():
+        state["x"] = api.inverse_nonherm(D, precision="mixed", ns_steps=1)
+
+    ms, _ = _time_loop(torch, [f], steps, 2)
+    X = state["x"].to(torch.complex128)
+    resid = (torch.matmul(X, D.to(torch.complex128)) - torch.eye(n, device=dev)).abs().amax()
+    return {"nonherm_c64_8x8_inv_per_s": count / (ms / 1e3),
+            "nonherm_c64_8x8_max_resid": float(resid)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -384,6 +404,7 @@ def main():
 
     if not args.no_extras:
         details.update(solve_workload(torch, api, [A8, A16], max(3, args.steps // 2)))
+        details.update(nonherm_workload(torch, api, dev, max(3, args.steps // 2)))
     if not args.no_extras and not args.no_large:
         details.update(large_workloads(torch, api, G, dev, max(2, args.steps // 4)))
     if not args.no_extras:
