@@ -232,11 +232,14 @@ def solve_workload(torch, api, mats, steps):
 def nonherm_workload(torch, api, dev, steps):
     """General (non-Hermitian) complex64 8 x 8 inverses through D D^* (Section
     III.C), 524,288 per batch, mixed precision with one refinement step; the
-    left-inverse residual max |X D - I| over the batch."""
+    left-inverse residual max |X D - I| over the batch.  D = I + E with
+    ||E||_2 about 0.35, so kappa(D) stays below about 2 and kappa(D D^*)
+    below about 5 for every matrix of the batch."""
     n, count = 8, 1 << 19
     g = torch.Generator(device=dev).manual_seed(5)
     D = torch.randn((count, n, n), dtype=torch.complex64, device=dev, generator=g)
-    D += (n ** 0.5) * torch.eye(n, dtype=torch.complex64, device=dev)
+    D *= 0.125 / n ** 0.5
+    D += torch.eye(n, dtype=torch.complex64, device=dev)
     state = {}
 
     def f():
