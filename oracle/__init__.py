@@ -69,6 +69,9 @@ def _load():
         getattr(lib, "or_grad_batched_" + sfx).argtypes = [_i64, _i32, _vp, _vp, _vp]
         for name in ("chol", "ldl", "inv_prop", "inv_eqsolve", "inv_tri", "gauss_jordan"):
             getattr(lib, "or_%s_%s" % (name, sfx)).restype = _i32
+    lib.or_inv_q15.argtypes = [_i32, _vp, _vp, _vp, _vp]
+    lib.or_inv_q15.restype = _i32
+    lib.or_inv_q15_batched.argtypes = [_i64, _i32, _vp, _vp, _vp, _vp, _vp]
     lib.or_inv_nonherm_z.argtypes = [_i32, _vp, _vp]
     lib.or_inv_nonherm_z.restype = _i32
     lib.or_herm_eig_z.argtypes = [_i32, _vp, _i64, _vp]
@@ -193,6 +196,30 @@ def inv_nonherm(d):
     out = np.zeros_like(d)
     info = _load().or_inv_nonherm_z(d.shape[-1], _p(d), _p(out))
     return out, int(info)
+
+
+def inv_q15(q):
+    """Fixed-point form of the proposed inversion (eqs. 3-4 and Section IV.A in
+    Q15 with Q30 sums, integer square root and rounded integer division; the
+    format is this implementation's reading).  q: int16 [batch, n, n, 2]
+    (re, im) standing for q / 2^15.  Returns (x int16 [batch, n, n, 2], xexp,
+    sat, info int32 [batch]) with A^{-1} ~ x 2^xexp."""
+    q = np.ascontiguousarray(q, dtype=np.int16)
+    if q.ndim == 3:
+        q = q[None]
+    batch, n = q.shape[0], q.shape[1]
+    x = np.zeros_like(q)
+    xexp = np.zeros(batch, np.int32)
+    sat = np.zeros(batch, np.int32)
+    info = np.zeros(batch, np.int32)
+    _load().or_inv_q15_batched(batch, n, _p(q), _p(x), _p(xexp), _p(sat), _p(info))
+    return x, xexp, sat, info
+
+
+def dequant_q15(x, xexp):
+    """complex128 values x 2^xexp of int16 (re, im) mantissas [batch, n, n, 2]."""
+    x = np.asarray(x, np.float64)
+    return (x[..., 0] + 1j * x[..., 1]) * np.ldexp(1.0, np.asarray(xexp))[:, None, None]
 
 
 # --------------------------------------------------------------------------

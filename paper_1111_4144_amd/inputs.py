@@ -190,3 +190,21 @@ def random_hpd(rng, count, n, shift=1.0, complex_=True, dtype=None):
     idx = np.arange(n)
     a[:, idx, idx] += shift
     return hermitize(a).astype(dtype or np.float64)
+
+
+def quantize_q15(a):
+    """Complex (or real) matrices [batch, n, n] to Q15 mantissas int16
+    [batch, n, n, 2] (re, im) with one power-of-two scale per matrix: a =
+    q 2^(e - 15), e the smallest integer with max |re|, |im| < 2^e, values
+    rounded to nearest and clipped to +-32767.  Returns (q, e)."""
+    a = np.asarray(a)
+    a = a.astype(np.complex128)
+    if a.ndim == 2:
+        a = a[None]
+    peak = np.maximum(np.abs(a.real), np.abs(a.imag)).max(axis=(-1, -2))
+    e = np.floor(np.log2(np.maximum(peak, np.finfo(np.float64).tiny))).astype(np.int32) + 1
+    scale = np.ldexp(1.0, 15 - e)[:, None, None]
+    q = np.empty(a.shape + (2,), np.int16)
+    q[..., 0] = np.clip(np.rint(a.real * scale), -32767, 32767)
+    q[..., 1] = np.clip(np.rint(a.imag * scale), -32767, 32767)
+    return q, e

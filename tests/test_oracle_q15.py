@@ -1,0 +1,100 @@
+"""Pins of the oracle's fixed-point (Q15 / Q30-sum) form of the proposed
+inversion, against facts fixed outside it:
+
+* diagonal inputs whose entries are powers of four have exact Q15 square
+  roots and exactly representable inverses: the result must be exact;
+* on MIMO-like inputs (and random Hermitian ones of every order up to 16) the
+  dequantized inverse must agree with the FP64 oracle's inverse of the same
+  quantized matrix to 4 kappa n 2^-15: every rounding is absolute (half a
+  Q15 unit, two per entry and step), the inputs are scaled so that their
+  largest entry is at least 1/2, so the backward error relative to ||A||_2 is
+  at most 2 * 2 n 2^-16 / (1/2), amplified by the condition number;
+* the output is Hermitian bit for bit; a clearly indefinite input fails at the
+  pivot the FP64 factorisation names; a hand-worked 2 x 2 case saturates its
+  off-diagonal factor entry and the saturation is counted.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1111_4144_amd import inputs as G
+from tests.helpers import kappas
+
+
+def _values(q):
+    return (q[..., 0] + 1j * q[..., 1]).astype(np.complex128) / 2.0 ** 15
+
+
+def test_q15_diagonal_powers_of_four_exact():
+    n = 7
+    q = np.zeros((1, n, n, 2), np.int16)
+    pw = [13, 11, 9, 7, 5, 13, 3]
+    for i, p in enumerate(pw):
+        q[0, i, i, 0] = 1 << p                   # a_ii = 2^(p - 15), an even power of two
+    x, xe, sat, info = O.inv_q15(q)
+    assert info[0] == 0 and sat[0] == 0
+    got = O.dequant_q15(x, xe)[0]
+    want = np.diag([2.0 ** (15 - p) for p in pw])
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("n", [8, 16])
+def test_q15_mimo_within_fixed_point_bound(n):
+    a = G.mimo(n, 300, seed=77)
+    q, _ = G.quantize_q15(a)
+    x, xe, sat, info = O.inv_q15(q)
+    assert (info == 0).all()
+    at = _values(q)
+    ref = np.stack([O.inv_prop(m)[0] for m in at])
+    got = O.dequant_q15(x, xe)
+    err = np.linalg.norm(got - ref, axis=(1, 2)) / np.linalg.norm(ref, axis=(1, 2))
+    bound = 4 * kappas(at) * n * 2.0 ** -15
+    assert (err <= bound).all(), (err / bound).max()
+
+
+def test_q15_random_orders_within_bound():
+    rng = np.random.default_rng(3)
+    for n in range(1, 17):
+        a = G.random_hpd(rng, 20, n, shift=0.3 * n)
+        q, _ = G.quantize_q15(a)
+        x, xe, sat, info = O.inv_q15(q)
+        assert (info == 0).all()
+        at = _values(q)
+        ref = np.stack([O.inv_prop(m)[0] for m in at])
+        got = O.dequant_q15(x, xe)
+        err = np.linalg.norm(got - ref, axis=(1, 2)) / np.linalg.norm(ref, axis=(1, 2))
+        assert (err <= 4 * kappas(at) * n * 2.0 ** -15).all(), n
+
+
+def test_q15_output_hermitian_bitwise():
+    q, _ = G.quantize_q15(G.mimo(12, 40, seed=5))
+    x, _, _, _ = O.inv_q15(q)
+    xt = np.swapaxes(x, 1, 2)
+    assert np.array_equal(x[..., 0], xt[..., 0])
+    assert np.array_equal(x[..., 1], -xt[..., 1])
+    assert (np.diagonal(x[..., 1], axis1=1, axis2=2) == 0).all()
+
+
+def test_q15_indefinite_fails_at_the_fp64_pivot():
+    a = G.random_hpd(np.random.default_rng(9), 1, 6, shift=1.0)[0]
+    a[3, 3] = -a[3, 3]                            # row 4's radicand is clearly negative
+    q, _ = G.quantize_q15(a)
+    _, info64 = O.chol(_values(q)[0])
+    x, xe, sat, info = O.inv_q15(q)
+    assert info64 == 4 and info[0] == 4
+    assert (x == 0).all()
+
+
+def test_q15_saturation_is_counted():
+    # a = [[32766, 32766], [32766, 32767]] / 2^15 (real):
+    # r_00 = floor(sqrt(32766 * 2^15)) = 32766 since 32767^2 = 32766 * 2^15 + 1;
+    # r_01 = round(32766 * 2^15 / 32766) = 32768, one above the Q15 range;
+    # r_11 = floor(sqrt(32767 * 2^15 - 32767^2)) = floor(sqrt(32767)) = 181
+    q = np.zeros((1, 2, 2, 2), np.int16)
+    q[0, :, :, 0] = [[32766, 32766], [32766, 32767]]
+    x, xe, sat, info = O.inv_q15(q)
+    assert info[0] == 0
+    assert sat[0] >= 1
+    # the inverse's (1, 1) entry is 1 / r_11^2 (in units of 2^-30 / 2^-30)
+    got = O.dequant_q15(x, xe)[0]
+    assert abs(got[1, 1].real - (2.0 ** 15 / 181) ** 2) <= 1e-3 * (2.0 ** 15 / 181) ** 2
