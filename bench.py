@@ -15,8 +15,9 @@ The printed JSON line also carries
                 from HIP events on its stream; algorithmic bytes per launch)
   cpu_baseline  the FP64 CPU oracle, single-threaded, on a bounded sample
   details       per-order rates, the plain-FP64 path on the same matrices, the
-                measured errors against the oracle, the differentiation
-                workload (forward + backward), and the other workloads.
+                measured errors against FP64 library inverses (the oracle is
+                used by the CPU baseline only), the differentiation workload
+                (forward + backward), and the other workloads.
 """
 from __future__ import annotations
 
@@ -62,14 +63,28 @@ def _time_loop(torch, fns, steps, warmup):
     return step_ms, launch_ms
 
 
-def _errors(x, a, oracle, idx):
-    """max relative Frobenius error and max err/kappa over sampled matrices."""
-    xo, _ = oracle.inv_prop(a[idx])
-    xs = x[idx].astype(np.complex128)
-    num = np.sqrt(np.sum(np.abs(xs - xo) ** 2, axis=(-1, -2)))
-    den = np.sqrt(np.sum(np.abs(xo) ** 2, axis=(-1, -2)))
-    err = num / den
-    kap = np.array([oracle.kappa2(m.astype(np.complex128)) for m in a[idx]])
+def _ref_inv(a):
+    """FP64 reference inverses from the CPU linear-algebra library (LU), for the
+    accuracy figures reported next to the timings."""
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a).astype(
+        np.complex128 if np.iscomplexobj(a) else np.float64))
+    return torch.linalg.inv(t).numpy()
+
+
+def _rel(x, ref):
+    num = np.sqrt(np.sum(np.abs(x - ref) ** 2, axis=(-1, -2)))
+    return num / np.sqrt(np.sum(np.abs(ref) ** 2, axis=(-1, -2)))
+
+
+def _errors(x, a, idx):
+    """max relative Frobenius error and max err/kappa over sampled matrices
+    (reference: FP64 library inverse; kappa from FP64 library eigenvalues)."""
+    import torch
+    am = a[idx].astype(np.complex128)
+    err = _rel(x[idx].astype(np.complex128), _ref_inv(am))
+    ev = torch.linalg.eigvalsh(torch.from_numpy(am)).numpy()
+    kap = ev[:, -1] / ev[:, 0]
     return float(err.max()), float((err / kap).max())
 
 
@@ -149,7 +164,7 @@ def large_workloads(torch, api, G, dev, steps):
     return out
 
 
-def varlen_workload(torch, api, G, O, dev, steps):
+def varlen_workload(torch, api, G, dev, steps):
     """262,144 real FP32 SPD matrices of orders U{2..64} in one packed buffer,
     one persistent launch (device bucketing prologue included), eager and as a
     replayed graph.  Bytes: A in + X out = 8 N^2 per matrix."""
@@ -182,7 +197,7 @@ def varlen_workload(torch, api, G, O, dev, steps):
     for b in range(0, count, count // 256):
         n, o = int(sizes[b]), int(offsets[b])
         am = packed[o:o + n * n].reshape(n, n).astype(np.float64)
-        xo, _ = O.inv_prop(am)
+        xo = _ref_inv(am)
         xm = x[o:o + n * n].reshape(n, n)
         worst = max(worst, float(np.linalg.norm(xm - xo) / np.linalg.norm(xo)))
     del P, S, OF, XV, ws
@@ -193,14 +208,14 @@ def varlen_workload(torch, api, G, O, dev, steps):
             "varlen_sampled_max_rel_err": worst}
 
 
-def plain_small_workload(torch, api, G, O, dev, steps):
-    """4096 complex128 4x4 matrices, plain FP64 (the oracle's own case): launch
-    time and error against the oracle."""
+def plain_small_workload(torch, api, G, dev, steps):
+    """4096 complex128 4x4 matrices, plain FP64: launch time and error against
+    the FP64 library inverse."""
     a = G.plain_fp64_4x4()
     A = torch.from_numpy(a).to(dev)
     X = torch.empty_like(A)
     ms, _ = _time_loop(torch, [lambda: api.inverse(A, out=X)], steps * 10, 5)
-    xo, _ = O.inv_prop(a)
+    xo = _ref_inv(a)
     x = X.cpu().numpy()
     err = np.sqrt(np.sum(np.abs(x - xo) ** 2, axis=(-1, -2))) / \
         np.sqrt(np.sum(np.abs(xo) ** 2, axis=(-1, -2)))
@@ -252,6 +267,32 @@ def nonherm_workload(torch, api, dev, steps):
             "nonherm_c64_8x8_max_resid": float(resid)}
 
 
+def q15_workload(torch, api, G, dev, steps):
+    """Fixed-point inversion of the 8 x 8 half of the MIMO batch quantized to
+    Q15 (524,288 matrices): rate, and the average relative Frobenius error
+    against the FP64 inverse of the quantized matrices over a sample (the
+    error measure of the paper's fixed-point comparison)."""
+    n, count = 8, 1 << 19
+    q, _ = G.quantize_q15(G.mimo(n, count))
+    Q = torch.from_numpy(q).to(dev)
+    state = {}
+
+    def f():
+        state["r"] = api.inverse_q15(Q)
+
+    ms, _ = _time_loop(torch, [f], steps, 2)
+    x, xe = (t.cpu().numpy() for t in state["r"])
+    idx = np.arange(0, count, count // 2048)
+    at = (q[idx, ..., 0] + 1j * q[idx, ..., 1]).astype(np.complex128) / 2.0 ** 15
+    ref = _ref_inv(at)
+    xs = x[idx].astype(np.float64)
+    got = (xs[..., 0] + 1j * xs[..., 1]) * np.ldexp(1.0, xe[idx])[:, None, None]
+    err = _rel(got, ref)
+    return {"q15_c64_8x8_inv_per_s": count / (ms / 1e3),
+            "q15_c64_8x8_avg_norm_err": float(err.mean()),
+            "q15_c64_8x8_max_norm_err": float(err.max())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -288,12 +329,11 @@ def main():
         print(json.dumps({"copy_bytes_per_launch": src.numel() * 4, "launches": 3}))
         return
 
-    import oracle as O
     from paper_1111_4144_amd import api, inputs as G
 
     if args.only:
         fn = {"large": lambda: large_workloads(torch, api, G, dev, max(2, args.steps // 4)),
-              "varlen": lambda: varlen_workload(torch, api, G, O, dev, max(3, args.steps // 2))}
+              "varlen": lambda: varlen_workload(torch, api, G, dev, max(3, args.steps // 2))}
         print(json.dumps({"only": args.only, "details": fn[args.only]()}), flush=True)
         return
 
@@ -348,14 +388,14 @@ def main():
         "tuned_engine_8x8": tuned[8], "tuned_engine_16x16": tuned[16],
     }
 
-    # accuracy of the timed outputs against the oracle (sampled matrices)
+    # accuracy of the timed outputs against FP64 library inverses (sampled matrices)
     rng = np.random.default_rng(0)
     idx8 = rng.choice(COUNT_PER_ORDER, 1024, replace=False)
     idx16 = rng.choice(COUNT_PER_ORDER, 1024, replace=False)
     x8 = X8.cpu().numpy()
     x16 = X16.cpu().numpy()
-    e8, r8 = _errors(x8, a8, O, idx8)
-    e16, r16 = _errors(x16, a16, O, idx16)
+    e8, r8 = _errors(x8, a8, idx8)
+    e16, r16 = _errors(x16, a16, idx16)
     details["mixed_max_rel_err"] = max(e8, e16)
     details["mixed_max_err_over_kappa"] = max(r8, r16)
     del x8, x16
@@ -369,8 +409,8 @@ def main():
         p_ms, (p8, p16) = _time_loop(
             torch, [lambda: api.inverse(B8, out=Y8), lambda: api.inverse(B16, out=Y16)],
             max(3, args.steps // 2), 2)
-        pe8, pr8 = _errors(Y8.cpu().numpy(), a8, O, idx8)
-        pe16, pr16 = _errors(Y16.cpu().numpy(), a16, O, idx16)
+        pe8, pr8 = _errors(Y8.cpu().numpy(), a8, idx8)
+        pe16, pr16 = _errors(Y16.cpu().numpy(), a16, idx16)
         details["plain_fp64_inv_per_s"] = total / (p_ms / 1e3)
         details["plain_fp64_max_rel_err"] = max(pe8, pe16)
         details["speedup_mixed_vs_plain_fp64"] = p_ms / step_ms
@@ -398,8 +438,9 @@ def main():
         details["grad16_bwd_hbm_frac"] = ag.shape[0] * 6144 / (gb / 1e3) / HBM_PEAK
         ga = state["ga"].cpu().numpy()
         sub = np.arange(0, ag.shape[0], 64)
-        xo, _ = O.inv_prop(ag[sub])
-        want = O.grad(xo, gg[sub])
+        xo = _ref_inv(ag[sub])
+        gh = 0.5 * (gg[sub] + np.conj(np.swapaxes(gg[sub], -1, -2)))
+        want = -(xo @ gh @ xo)
         gerr = np.sqrt(np.sum(np.abs(ga[sub] - want) ** 2, axis=(-1, -2))) / \
             np.sqrt(np.sum(np.abs(want) ** 2, axis=(-1, -2)))
         details["grad16_max_rel_err"] = float(gerr.max())
@@ -408,11 +449,12 @@ def main():
     if not args.no_extras:
         details.update(solve_workload(torch, api, [A8, A16], max(3, args.steps // 2)))
         details.update(nonherm_workload(torch, api, dev, max(3, args.steps // 2)))
+        details.update(q15_workload(torch, api, G, dev, max(3, args.steps // 2)))
     if not args.no_extras and not args.no_large:
         details.update(large_workloads(torch, api, G, dev, max(2, args.steps // 4)))
     if not args.no_extras:
-        details.update(varlen_workload(torch, api, G, O, dev, max(3, args.steps // 2)))
-        details.update(plain_small_workload(torch, api, G, O, dev, max(3, args.steps // 2)))
+        details.update(varlen_workload(torch, api, G, dev, max(3, args.steps // 2)))
+        details.update(plain_small_workload(torch, api, G, dev, max(3, args.steps // 2)))
 
     line = {
         "metric": "inverses/s (8x8 c64 batch), TFLOP/s N=8192, fwd+bwd vs plain @ stated err",

@@ -236,6 +236,40 @@ int chol_inverse_nonherm(int dtype, int64_t batch, int64_t n, const void* d, int
 int chol_inverse_backward(int dtype, int64_t batch, int64_t n, const void* x, const void* g,
                           void* ga, int64_t stride, void* stream);
 
+/*
+ * chol_inverse_q15 -- the proposed inversion in fixed point, for batches of
+ * complex Hermitian positive-definite matrices of order n <= CI_Q15_NMAX
+ * (Cholesky, eqs. 3-4; Section IV.A back-substitution; mirror).  The paper
+ * evaluates its method by fixed-point simulation without naming a format;
+ * this one is:
+ *   - input entries are int16 (re, im) pairs q standing for q / 2^15 (scale
+ *     each matrix by a power of two beforehand; the inverse scales back by
+ *     the inverse power); only the upper triangle is read, the imaginary part
+ *     of the diagonal is ignored;
+ *   - R is held in Q15 and saturates at +-32767; every sum of products is an
+ *     int64 with 30 fractional bits; r_ii = floor(sqrt(radicand)) exactly;
+ *     off-diagonal entries divide by r_ii with rounding to nearest, halves
+ *     away from zero (as every rounding here);
+ *   - X is formed as X 2^F in int64, F = 2 floor(log2 min r_ii) -
+ *     ceil(log2 n), saturating at +-(2^40 - 1);
+ *   - the output is int16 (re, im) mantissas x with X = x 2^xexp (xexp per
+ *     matrix, the smallest shift that fits), written in full with x_ji =
+ *     conj(x_ij).
+ *   batch        number of matrices (<= 2^36)
+ *   n            order, 0 <= n <= CI_Q15_NMAX
+ *   a, stride    device int16, matrix b at a + 2*b*stride (stride in complex
+ *                entries, >= n*n; ignored when batch == 1), leading dimension n
+ *   x            device int16 output, same layout; must not equal a
+ *   xexp         device int32[batch], required
+ *   sat          device int32[batch] or NULL: saturation events per matrix
+ *   info         device int32[batch] or NULL: 0, or the 1-based row whose
+ *                radicand is <= 0 (then x = 0 and xexp = 0)
+ * Results are exact integers: they do not depend on the device or the launch.
+ */
+#define CI_Q15_NMAX 16
+int chol_inverse_q15(int64_t batch, int64_t n, const int16_t* a, int64_t stride, int16_t* x,
+                     int32_t* xexp, int32_t* sat, int32_t* info, void* stream);
+
 /* Which entry point a workspace query is for. */
 enum { CI_FN_FACTOR = 0, CI_FN_INVERSE = 1, CI_FN_BATCHED = 2, CI_FN_NONHERM = 3 };
 

@@ -272,6 +272,32 @@ def inverse_nonherm(D: torch.Tensor, *, method="chol", precision="plain", ns_ste
     return (X, info.reshape(D.shape[:-2])) if return_info else X
 
 
+def inverse_q15(Q: torch.Tensor, *, return_info=False):
+    """Fixed-point inversion of complex Hermitian matrices given as int16
+    mantissas Q[..., n, n, 2] (re, im; value Q / 2^15), n <= 16: Cholesky and
+    the Section IV.A back-substitution in Q15 storage with int64 Q30 sums.
+    Returns (X int16 [..., n, n, 2], xexp int32 [...]) with A^{-1} = X 2^xexp,
+    plus (sat, info) with return_info."""
+    _check_device(Q)
+    if Q.dtype != torch.int16 or Q.shape[-1] != 2 or Q.shape[-2] != Q.shape[-3]:
+        raise TypeError("Q must be int16 [..., n, n, 2]")
+    n = Q.shape[-2]
+    Q4 = Q.reshape(-1, n, n, 2).contiguous()
+    B = Q4.shape[0]
+    X = torch.empty_like(Q4)
+    xexp = torch.zeros(B, dtype=torch.int32, device=Q.device)
+    sat = torch.zeros(B, dtype=torch.int32, device=Q.device)
+    info = torch.zeros(B, dtype=torch.int32, device=Q.device)
+    rc = L.lib().chol_inverse_q15(B, n, _ptr(Q4), n * n, _ptr(X), _ptr(xexp), _ptr(sat),
+                                  _ptr(info), _stream(Q.device))
+    L.check("chol_inverse_q15", rc)
+    X = X.reshape(Q.shape)
+    lead = Q.shape[:-3]
+    if return_info:
+        return X, xexp.reshape(lead), sat.reshape(lead), info.reshape(lead)
+    return X, xexp.reshape(lead)
+
+
 _DT_CODE = {"f32": L.CI_F32, "f64": L.CI_F64, "c64": L.CI_C64, "c128": L.CI_C128}
 
 

@@ -8,6 +8,7 @@
 #include "ci_launch.hpp"
 #include "ci_large.hpp"
 #include "ci_nonherm.hpp"
+#include "ci_q15.hpp"
 #include "cholinv.h"
 
 namespace {
@@ -162,6 +163,21 @@ int chol_inverse_nonherm(int dtype, int64_t batch, int64_t n, const void* d, int
     e = run_small(dtype, n, ci::OP_INV, o.method, o.precision == CI_MIXED, p, s);
     if (e != hipSuccess) return map_err(e);
     return map_err(ci::launch_adjoint_product(dtype, d, sd, xa, x, sd, batch, (int)n, s));
+}
+
+int chol_inverse_q15(int64_t batch, int64_t n, const int16_t* a, int64_t stride, int16_t* x,
+                     int32_t* xexp, int32_t* sat, int32_t* info, void* stream)
+{
+    if (batch < 0 || batch > ((int64_t)1 << 36)) return -1;
+    if (n < 0 || n > CI_Q15_NMAX) return -2;
+    const bool work = batch > 0 && n > 0;
+    if (work && !a) return -3;
+    if (batch > 1 && stride < n * n) return -4;
+    if (work && (!x || x == a)) return -5;
+    if (work && !xexp) return -6;
+    if (!work) return (batch > 0 && info) ? map_err(ci::fill_i32(info, batch, 0, (hipStream_t)stream)) : 0;
+    return map_err(ci::launch_inv_q15(a, batch > 1 ? stride : n * n, x, xexp, sat, info, batch,
+                                      (int)n, (hipStream_t)stream));
 }
 
 int chol_inverse(int dtype, int64_t n, const void* a, int64_t lda, void* x, int64_t ldx,

@@ -1,0 +1,14 @@
+// ci_q15.hpp -- launcher of the fixed-point inversion (internal to libcholinv).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ci {
+
+// Q15 inversion of `batch` complex Hermitian matrices of order n <= 16
+// (int16 (re, im) pairs, matrix b at a + 2*b*stride, leading dimension n).
+hipError_t launch_inv_q15(const int16_t* a, int64_t stride, int16_t* x, int32_t* xexp,
+                          int32_t* sat, int32_t* info, int64_t batch, int n, hipStream_t s);
+
+}  // namespace ci

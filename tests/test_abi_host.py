@@ -87,6 +87,10 @@ def test_argument_validation_codes():
     assert lib.chol_inverse_nonherm(0, 2, 4, p, 16, q, None, p, 255, None, None) == \
         L.CI_ERR_WORKSPACE
     assert lib.chol_workspace_size(L.CI_FN_NONHERM, 0, 2, 4, None) == 512
+    # fixed point: order beyond 16, output = input, exponent array missing
+    assert lib.chol_inverse_q15(2, 17, p, 17 * 17, q, q, None, None, None) == -2
+    assert lib.chol_inverse_q15(2, 4, p, 16, p, q, None, None, None) == -5
+    assert lib.chol_inverse_q15(2, 4, p, 16, q, None, None, None, None) == -6
     # empty work is a no-op
     assert lib.chol_inverse_batched(2, 0, 4, None, None, 0, None, 16, None, 16, None, None, 0,
                                     None, None) == 0
