@@ -80,7 +80,7 @@ int or_inv_q15(int n, const int16_t* a, int16_t* x, int32_t* xexp, int32_t* sat_
 
     /* eqs. (3)-(4), row by row */
     for (int i = 0; i < n; ++i) {
-        int64_t acc = A_RE(i, i) << 15;                        /* Q30 */
+        int64_t acc = A_RE(i, i) * 32768;                      /* Q30 */
         for (int k = 0; k < i; ++k)
             acc -= rr[IX(k, i)] * rr[IX(k, i)] + ri[IX(k, i)] * ri[IX(k, i)];
         if (acc <= 0) {
@@ -91,7 +91,7 @@ int or_inv_q15(int n, const int16_t* a, int16_t* x, int32_t* xexp, int32_t* sat_
         rr[IX(i, i)] = d;
         ri[IX(i, i)] = 0;
         for (int j = i + 1; j < n; ++j) {
-            int64_t sr = A_RE(i, j) << 15, si = A_IM(i, j) << 15;
+            int64_t sr = A_RE(i, j) * 32768, si = A_IM(i, j) * 32768;
             for (int k = 0; k < i; ++k) {                      /* conj(r_ki) r_kj */
                 sr -= rr[IX(k, i)] * rr[IX(k, j)] + ri[IX(k, i)] * ri[IX(k, j)];
                 si -= rr[IX(k, i)] * ri[IX(k, j)] - ri[IX(k, i)] * rr[IX(k, j)];
