@@ -293,6 +293,31 @@ def q15_workload(torch, api, G, dev, steps):
             "q15_c64_8x8_max_norm_err": float(err.max())}
 
 
+def compare_workload(torch, api, a8, A8, steps):
+    """Side by side on the 8 x 8 half of the MIMO batch (524,288 complex64,
+    plain FP32 arithmetic): the Section III.A and III.B comparison kernels and
+    the proposed method's plain-FP32 engine; rates and sampled errors against
+    FP64 library inverses (the comparison kernels are straightforward one-lane
+    implementations, so their rates are context, not tuned baselines)."""
+    out = {}
+    idx = np.arange(0, a8.shape[0], a8.shape[0] // 1024)
+    ref = _ref_inv(a8[idx])
+    cases = [("IV", lambda: api.inverse(A8)),
+             ("IIIA", lambda: api.inverse_compare(A8, variant="III.A")),
+             ("IIIB", lambda: api.inverse_compare(A8, variant="III.B"))]
+    for name, fn in cases:
+        state = {}
+
+        def f():
+            state["x"] = fn()
+
+        ms, _ = _time_loop(torch, [f], steps, 1)
+        x = state["x"][idx].cpu().numpy().astype(np.complex128)
+        out["compare_c64_8x8_%s_plain_inv_per_s" % name] = a8.shape[0] / (ms / 1e3)
+        out["compare_c64_8x8_%s_plain_avg_rel_err" % name] = float(_rel(x, ref).mean())
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -450,6 +475,7 @@ def main():
         details.update(solve_workload(torch, api, [A8, A16], max(3, args.steps // 2)))
         details.update(nonherm_workload(torch, api, dev, max(3, args.steps // 2)))
         details.update(q15_workload(torch, api, G, dev, max(3, args.steps // 2)))
+        details.update(compare_workload(torch, api, a8, A8, max(3, args.steps // 4)))
     if not args.no_extras and not args.no_large:
         details.update(large_workloads(torch, api, G, dev, max(2, args.steps // 4)))
     if not args.no_extras:

@@ -270,6 +270,29 @@ int chol_inverse_backward(int dtype, int64_t batch, int64_t n, const void* x, co
 int chol_inverse_q15(int64_t batch, int64_t n, const int16_t* a, int64_t stride, int16_t* x,
                      int32_t* xexp, int32_t* sat, int32_t* info, void* stream);
 
+/*
+ * chol_inverse_compare -- the existing methods the paper compares against,
+ * for batches of small matrices (orders <= CI_COMPARE_NMAX), arithmetic in the
+ * element type, one lane per matrix (straightforward kernels for accuracy and
+ * timing comparisons, not tuned):
+ *   CI_III_A  Section III.A, equation solving: A x_i = e_i (eq. 15) for the
+ *             upper half of each column, after a Cholesky (method
+ *             CI_METHOD_CHOL) or LDL (CI_METHOD_LDL) factorisation
+ *   CI_III_B  Section III.B, triangular operations: M = R^{-1} (eq. 18), then
+ *             the upper half of X = M M^* (eq. 19); Cholesky only
+ *   a, stride  device input, matrix b at a + b*stride (stride >= n*n;
+ *              ignored when batch == 1), leading dimension n; upper triangle
+ *              read
+ *   x          device output, same layout, written in full (mirrored); must
+ *              not equal a
+ *   info       device int32[batch] or NULL: first failing 1-based pivot (not
+ *              a finite positive number); the X of a failed matrix is NaN
+ */
+#define CI_COMPARE_NMAX 16
+enum { CI_III_A = 0, CI_III_B = 1 };
+int chol_inverse_compare(int dtype, int variant, int method, int64_t batch, int64_t n,
+                         const void* a, int64_t stride, void* x, int32_t* info, void* stream);
+
 /* Which entry point a workspace query is for. */
 enum { CI_FN_FACTOR = 0, CI_FN_INVERSE = 1, CI_FN_BATCHED = 2, CI_FN_NONHERM = 3 };
 

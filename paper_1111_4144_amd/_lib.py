@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libcholinv.so")
 
 CI_F32, CI_F64, CI_C64, CI_C128 = 0, 1, 2, 3
 CI_METHOD_CHOL, CI_METHOD_LDL = 0, 1
+CI_III_A, CI_III_B = 0, 1
 CI_PLAIN, CI_MIXED = 0, 1
 CI_FN_FACTOR, CI_FN_INVERSE, CI_FN_BATCHED, CI_FN_NONHERM = 0, 1, 2, 3
 CI_ERR_UNSUPPORTED = -2000
@@ -23,8 +24,8 @@ CI_SMALL_NMAX = 64
 
 # Every symbol include/cholinv.h declares.
 EXPORTS = ("chol_factor", "ldl_factor", "chol_solve", "chol_inverse", "chol_inverse_batched",
-           "chol_inverse_nonherm", "chol_inverse_q15", "chol_inverse_backward",
-           "chol_workspace_size",
+           "chol_inverse_nonherm", "chol_inverse_q15", "chol_inverse_compare",
+           "chol_inverse_backward", "chol_workspace_size",
            "chol_status_string", "chol_version",
            "chol_autotune", "chol_tuned_engine", "chol_autotune_clear")
 
@@ -67,6 +68,7 @@ def lib():
     L.chol_inverse_nonherm.argtypes = [_i32, _i64, _i64, _vp, _i64, _vp, ctypes.POINTER(ci_opts),
                                        _vp, _sz, _vp, _vp]
     L.chol_inverse_q15.argtypes = [_i64, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp]
+    L.chol_inverse_compare.argtypes = [_i32, _i32, _i32, _i64, _i64, _vp, _i64, _vp, _vp, _vp]
     L.chol_inverse_backward.argtypes = [_i32, _i64, _i64, _vp, _vp, _vp, _i64, _vp]
     L.chol_workspace_size.argtypes = [_i32, _i32, _i64, _i64, ctypes.POINTER(ci_opts)]
     L.chol_workspace_size.restype = _sz
@@ -78,7 +80,8 @@ def lib():
     L.chol_autotune_clear.argtypes = []
     L.chol_autotune_clear.restype = None
     for fn in ("chol_factor", "ldl_factor", "chol_solve", "chol_inverse", "chol_inverse_batched",
-               "chol_inverse_nonherm", "chol_inverse_q15", "chol_inverse_backward"):
+               "chol_inverse_nonherm", "chol_inverse_q15", "chol_inverse_compare",
+               "chol_inverse_backward"):
         getattr(L, fn).restype = _i32
     _lib = L
     return L

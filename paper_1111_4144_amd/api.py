@@ -298,6 +298,25 @@ def inverse_q15(Q: torch.Tensor, *, return_info=False):
     return X, xexp.reshape(lead)
 
 
+def inverse_compare(A: torch.Tensor, *, variant="III.A", method="chol", return_info=False):
+    """The comparison methods of Section III on the GPU (orders <= 16, element
+    type arithmetic): "III.A" equation solving (eq. 15; Cholesky or LDL) or
+    "III.B" triangular operations (eqs. 17-19; Cholesky).  X in full."""
+    _check_device(A)
+    var = {"III.A": L.CI_III_A, "III.B": L.CI_III_B}[variant]
+    meth = {"chol": L.CI_METHOD_CHOL, "ldl": L.CI_METHOD_LDL}[method]
+    n = A.shape[-1]
+    A3 = A.reshape(-1, n, n).contiguous()
+    B = A3.shape[0]
+    X = torch.empty_like(A3)
+    info = torch.zeros(B, dtype=torch.int32, device=A.device)
+    rc = L.lib().chol_inverse_compare(_dtype_code(A), var, meth, B, n, _ptr(A3), n * n, _ptr(X),
+                                      _ptr(info), _stream(A.device))
+    L.check("chol_inverse_compare", rc)
+    X = X.reshape(A.shape)
+    return (X, info.reshape(A.shape[:-2])) if return_info else X
+
+
 _DT_CODE = {"f32": L.CI_F32, "f64": L.CI_F64, "c64": L.CI_C64, "c128": L.CI_C128}
 
 

@@ -9,6 +9,7 @@
 #include "ci_large.hpp"
 #include "ci_nonherm.hpp"
 #include "ci_q15.hpp"
+#include "ci_compare.hpp"
 #include "cholinv.h"
 
 namespace {
@@ -178,6 +179,25 @@ int chol_inverse_q15(int64_t batch, int64_t n, const int16_t* a, int64_t stride,
     if (!work) return (batch > 0 && info) ? map_err(ci::fill_i32(info, batch, 0, (hipStream_t)stream)) : 0;
     return map_err(ci::launch_inv_q15(a, batch > 1 ? stride : n * n, x, xexp, sat, info, batch,
                                       (int)n, (hipStream_t)stream));
+}
+
+int chol_inverse_compare(int dtype, int variant, int method, int64_t batch, int64_t n,
+                         const void* a, int64_t stride, void* x, int32_t* info, void* stream)
+{
+    if (!valid_dtype(dtype)) return -1;
+    if (variant != CI_III_A && variant != CI_III_B) return -2;
+    if (method != CI_METHOD_CHOL && (method != CI_METHOD_LDL || variant != CI_III_A)) return -3;
+    if (batch < 0 || batch > ((int64_t)1 << 36)) return -4;
+    if (n < 0 || n > CI_COMPARE_NMAX) return -5;
+    const bool work = batch > 0 && n > 0;
+    if (work && !a) return -6;
+    if (batch > 1 && stride < n * n) return -7;
+    if (work && (!x || x == a)) return -8;
+    hipStream_t s = (hipStream_t)stream;
+    if (!work) return (batch > 0 && info) ? map_err(ci::fill_i32(info, batch, 0, s)) : 0;
+    const int k = variant == CI_III_B ? 2 : (method == CI_METHOD_LDL ? 1 : 0);
+    const int64_t st = batch > 1 ? stride : n * n;
+    return map_err(ci::launch_compare(dtype, k, a, st, x, st, info, batch, (int)n, s));
 }
 
 int chol_inverse(int dtype, int64_t n, const void* a, int64_t lda, void* x, int64_t ldx,
