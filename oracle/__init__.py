@@ -18,6 +18,7 @@ Functions and the passages they follow:
 * ``chol_solve``    Section II, eqs. (5)-(7)
 * ``ldl_solve``     Section II.A, eqs. (12)-(14)
 * ``inv_prop``      Section IV.A (method "chol", eq. 24) / IV.B ("ldl", eq. 29)
+* ``inv_prop_all_cores``  the same routine over a stack, matrices shared among threads
 * ``inv_eqsolve``   Section III.A, eq. (15)
 * ``inv_tri``       Section III.B, eqs. (16)-(19)
 * ``inv_nonherm``   Section III.C
@@ -66,6 +67,8 @@ def _load():
         getattr(lib, "or_gauss_jordan_" + sfx).argtypes = [_i32, _vp, _i64, _vp, _i64]
         getattr(lib, "or_inv_prop_batched_" + sfx).argtypes = [_i32, _i64, _i32, _vp, _vp, _vp]
         getattr(lib, "or_inv_prop_varlen_" + sfx).argtypes = [_i32, _i64, _vp, _vp, _vp, _vp, _vp]
+        getattr(lib, "or_inv_prop_batched_omp_" + sfx).argtypes = [_i32, _i64, _i32, _vp, _vp,
+                                                                   _vp]
         getattr(lib, "or_grad_batched_" + sfx).argtypes = [_i64, _i32, _vp, _vp, _vp]
         for name in ("chol", "ldl", "inv_prop", "inv_eqsolve", "inv_tri", "gauss_jordan"):
             getattr(lib, "or_%s_%s" % (name, sfx)).restype = _i32
@@ -77,6 +80,8 @@ def _load():
     lib.or_herm_eig_z.argtypes = [_i32, _vp, _i64, _vp]
     lib.or_herm_eig_z.restype = _i32
     lib.or_count_get.restype = ctypes.c_ulonglong
+    lib.or_set_threads.argtypes = [_i32]
+    lib.or_max_threads.restype = _i32
     _lib = lib
     return lib
 
@@ -157,6 +162,28 @@ def inv_prop(a, method="chol", fill_lower=True):
     getattr(lib, "or_inv_prop_batched_" + s)(_method(method), flat.shape[0], n, _p(flat),
                                              _p(x), _p(info))
     return x.reshape(a.shape), info.reshape(a.shape[:-2])
+
+
+def inv_prop_all_cores(a, threads, method="chol"):
+    """inv_prop over a stack (B, n, n) with the matrices shared out among
+    `threads` OpenMP threads (each matrix by the same single-threaded routine;
+    the results are those of inv_prop). Returns (X, info)."""
+    a, s = _prep(a)
+    lib = _load()
+    n = a.shape[-1]
+    flat = a.reshape(-1, n, n)
+    x = np.zeros_like(flat)
+    info = np.zeros(flat.shape[0], np.int32)
+    lib.or_set_threads(int(threads))
+    getattr(lib, "or_inv_prop_batched_omp_" + s)(_method(method), flat.shape[0], n, _p(flat),
+                                                 _p(x), _p(info))
+    return x.reshape(a.shape), info.reshape(a.shape[:-2])
+
+
+def build_flags():
+    """The compiler and flags the oracle library is built with."""
+    from . import build as _build
+    return "gcc " + " ".join(_build.CFLAGS)
 
 
 def inv_prop_varlen(packed, sizes, offsets, method="chol"):

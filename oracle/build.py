@@ -3,7 +3,9 @@
     python -m oracle.build        # writes oracle/libcholinv_oracle.so
 
 Compiled with plain gcc, no fast-math and no floating-point contraction, so
-every operation rounds as written in the C source.
+every operation rounds as written in the C source.  OpenMP is enabled only for
+the all-cores batch loop (or_inv_prop_batched_omp_*); every other routine is
+single-threaded.
 """
 import os
 import subprocess
@@ -14,7 +16,7 @@ SRC = os.path.join(HERE, "cholinv_oracle.c")
 SRC_Q15 = os.path.join(HERE, "cholinv_oracle_q15.c")
 LIB = os.path.join(HERE, "libcholinv_oracle.so")
 CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-          "-Wall", "-Wextra", "-Wno-unused-function"]
+          "-fopenmp", "-Wall", "-Wextra", "-Wno-unused-function"]
 
 
 def build(verbose: bool = False) -> str:

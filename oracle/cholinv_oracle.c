@@ -25,14 +25,19 @@
  *   or_gauss_jordan_*  brute-force inverse (independent route)
  *   or_herm_eig_z      cyclic Jacobi eigenvalues (for the 2-norm condition)
  *   or_count_reset / or_count_get   multiply counter (Table 1 convention)
- * Batched forms loop the single-matrix routine over a stack of matrices.
+ * Batched forms loop the single-matrix routine over a stack of matrices;
+ * or_inv_prop_batched_omp_* runs the same loop with OpenMP over matrices
+ * (each matrix still by the single-threaded routine), for the all-cores CPU
+ * baseline, with or_set_threads choosing the thread count.
  */
 #include <complex.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
-static unsigned long long g_mults = 0;
+/* one counter per thread, so that the all-cores batch loop below races on
+ * nothing; the counting tests read it from the thread that ran the routine */
+static _Thread_local unsigned long long g_mults = 0;
 
 void or_count_reset(void) { g_mults = 0; }
 unsigned long long or_count_get(void) { return g_mults; }
@@ -110,6 +115,14 @@ void or_inv_prop_varlen_##SUF(int method, long batch, const int* ns,           \
         info[b] = inv_prop_##SUF(method, ns[b], a + offs[b], ns[b],            \
                                  x + offs[b], ns[b], 1);                       \
 }                                                                              \
+void or_inv_prop_batched_omp_##SUF(int method, long batch, int n, const T* a,  \
+                                   T* x, int* info)                            \
+{                                                                              \
+    _Pragma("omp parallel for schedule(static)")                               \
+    for (long b = 0; b < batch; ++b)                                           \
+        info[b] = inv_prop_##SUF(method, n, a + b * (long)n * n, n,            \
+                                 x + b * (long)n * n, n, 1);                   \
+}                                                                              \
 void or_grad_batched_##SUF(long batch, int n, const T* x, const T* g, T* ga)   \
 {                                                                              \
     for (long b = 0; b < batch; ++b)                                           \
@@ -119,6 +132,15 @@ void or_grad_batched_##SUF(long batch, int n, const T* x, const T* g, T* ga)   \
 
 EXPORT_BOTH(d, double)
 EXPORT_BOTH(z, double complex)
+
+#ifdef _OPENMP
+#include <omp.h>
+void or_set_threads(int t) { omp_set_num_threads(t > 0 ? t : 1); }
+int or_max_threads(void) { return omp_get_max_threads(); }
+#else
+void or_set_threads(int t) { (void)t; }
+int or_max_threads(void) { return 1; }
+#endif
 
 /* Section III.C: for an arbitrary square D, A = D D^* is Hermitian           */
 /* positive definite when D is non-singular; D^{-1} = D^* A^{-1}.             */

@@ -173,6 +173,11 @@ def kms(n, rho, dtype=np.complex128):
     """Kac-Murdock-Szego matrix a_ij = rho^(j-i) for j >= i, a_ji = conj(a_ij)."""
     i = np.arange(n)
     p = np.maximum(i[None, :] - i[:, None], 0)
+    if np.isrealobj(rho) and not np.issubdtype(np.dtype(dtype), np.complexfloating):
+        # real rho, real storage: the symmetric matrix rho^|j-i| directly (no
+        # complex temporaries, which matter at orders in the thousands)
+        a = float(rho) ** np.abs(i[None, :] - i[:, None]).astype(np.float64)
+        return a.astype(dtype)
     a = np.asarray(rho, dtype=np.complex128) ** p
     a = hermitize(np.triu(a))
     if not np.issubdtype(np.dtype(dtype), np.complexfloating):
