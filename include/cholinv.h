@@ -31,6 +31,8 @@
  *    -k  (1 <= k < 100)    argument number k (1-based) is invalid
  *    CI_ERR_UNSUPPORTED    valid arguments but a combination this build lacks
  *    CI_ERR_WORKSPACE      work_bytes smaller than chol_workspace_size()
+ *    CI_ERR_NOALLOC_LIMIT  uneven batch above CI_NOALLOC_MAX_BATCH
+ *                          (allocation-free entry point only)
  *    CI_ERR_LAUNCH - e     a HIP launch failed with hipError_t e
  * Numerical failure is never a return code.  `info` (device int32, one per
  * matrix, may be NULL) receives 0, or the 1-based index i of the first pivot
@@ -78,6 +80,7 @@ typedef struct {
 
 #define CI_ERR_UNSUPPORTED (-2000)
 #define CI_ERR_WORKSPACE   (-2001)
+#define CI_ERR_NOALLOC_LIMIT (-2002)
 #define CI_ERR_LAUNCH      (-1000)
 
 /* Largest order handled by the batched small-matrix kernels (one matrix per
@@ -201,6 +204,32 @@ int chol_inverse_batched(int dtype, int64_t batch, int64_t n_uniform, const int3
                          const int64_t* offsets_dev, int64_t n_max, const void* a,
                          int64_t stride_a, void* x, int64_t stride_x, const ci_opts* opts,
                          void* work, size_t work_bytes, int32_t* info, void* stream);
+
+/*
+ * chol_inverse_batched_noalloc -- chol_inverse_batched for callers that cannot
+ * allocate or pass device memory for scratch: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Same arguments and
+ * results as chol_inverse_batched without work/work_bytes.  An uneven batch
+ * (n_uniform == 0) keeps its bucketing plan and sorted work list in a scratch
+ * array that the library holds in device memory, one per GPU, for the life of
+ * the process (CI_NOALLOC_MAX_BATCH * 4 bytes plus about 1.3 KiB); uniform
+ * batches need no scratch.  The call allocates nothing (no hipMalloc, no
+ * hipFree), does not synchronise and clears the plan with a kernel, so it may
+ * be captured; the first call on a device must not be captured (it looks up
+ * that device's array).  The device is the current one, and `stream` must
+ * belong to it.
+ *   batch       uneven batches: at most CI_NOALLOC_MAX_BATCH, else
+ *               CI_ERR_NOALLOC_LIMIT (checked before any other argument)
+ * Calls on one GPU share its array: two uneven-batch calls whose work may
+ * overlap in time on that GPU (different streams, or concurrent host
+ * threads) race on it and give undefined results; calls queued in order on
+ * one stream are safe.
+ */
+#define CI_NOALLOC_MAX_BATCH 2097152
+int chol_inverse_batched_noalloc(int dtype, int64_t batch, int64_t n_uniform,
+                                 const int32_t* n_dev, const int64_t* offsets_dev, int64_t n_max,
+                                 const void* a, int64_t stride_a, void* x, int64_t stride_x,
+                                 const ci_opts* opts, int32_t* info, void* stream);
 
 /*
  * chol_inverse_nonherm -- D_b^{-1} for a batch of general (not Hermitian)

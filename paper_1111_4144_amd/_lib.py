@@ -19,12 +19,14 @@ CI_PLAIN, CI_MIXED = 0, 1
 CI_FN_FACTOR, CI_FN_INVERSE, CI_FN_BATCHED, CI_FN_NONHERM = 0, 1, 2, 3
 CI_ERR_UNSUPPORTED = -2000
 CI_ERR_WORKSPACE = -2001
+CI_ERR_NOALLOC_LIMIT = -2002
+CI_NOALLOC_MAX_BATCH = 2097152
 CI_ERR_LAUNCH = -1000
 CI_SMALL_NMAX = 64
 
 # Every symbol include/cholinv.h declares.
 EXPORTS = ("chol_factor", "ldl_factor", "chol_solve", "chol_inverse", "chol_inverse_batched",
-           "chol_inverse_nonherm", "chol_inverse_q15", "chol_inverse_compare",
+           "chol_inverse_batched_noalloc", "chol_inverse_nonherm", "chol_inverse_q15", "chol_inverse_compare",
            "chol_inverse_backward", "chol_workspace_size",
            "chol_status_string", "chol_version",
            "chol_autotune", "chol_tuned_engine", "chol_autotune_clear")
@@ -65,6 +67,8 @@ def lib():
                                _sz, _vp, _vp]
     L.chol_inverse_batched.argtypes = [_i32, _i64, _i64, _vp, _vp, _i64, _vp, _i64, _vp, _i64,
                                        ctypes.POINTER(ci_opts), _vp, _sz, _vp, _vp]
+    L.chol_inverse_batched_noalloc.argtypes = [_i32, _i64, _i64, _vp, _vp, _i64, _vp, _i64, _vp,
+                                               _i64, ctypes.POINTER(ci_opts), _vp, _vp]
     L.chol_inverse_nonherm.argtypes = [_i32, _i64, _i64, _vp, _i64, _vp, ctypes.POINTER(ci_opts),
                                        _vp, _sz, _vp, _vp]
     L.chol_inverse_q15.argtypes = [_i64, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp]
@@ -80,7 +84,7 @@ def lib():
     L.chol_autotune_clear.argtypes = []
     L.chol_autotune_clear.restype = None
     for fn in ("chol_factor", "ldl_factor", "chol_solve", "chol_inverse", "chol_inverse_batched",
-               "chol_inverse_nonherm", "chol_inverse_q15", "chol_inverse_compare",
+               "chol_inverse_batched_noalloc", "chol_inverse_nonherm", "chol_inverse_q15", "chol_inverse_compare",
                "chol_inverse_backward"):
         getattr(L, fn).restype = _i32
     _lib = L

@@ -259,6 +259,25 @@ int chol_inverse_batched(int dtype, int64_t batch, int64_t n_uniform, const int3
     return map_err(run_small(dtype, n_uniform, ci::OP_INV, o.method, o.precision == CI_MIXED, p, s));
 }
 
+int chol_inverse_batched_noalloc(int dtype, int64_t batch, int64_t n_uniform,
+                                 const int32_t* n_dev, const int64_t* offsets_dev, int64_t n_max,
+                                 const void* a, int64_t stride_a, void* x, int64_t stride_x,
+                                 const ci_opts* opts, int32_t* info, void* stream)
+{
+    if (n_uniform == 0 && batch > CI_NOALLOC_MAX_BATCH) return CI_ERR_NOALLOC_LIMIT;
+    void* scratch = nullptr;
+    size_t bytes = 0;
+    if (n_uniform == 0 && batch > 0) {
+        // the varlen plan and work list go to the library-held array; uniform
+        // batches need no scratch (the call is then chol_inverse_batched's)
+        const hipError_t e = ci::noalloc_scratch(&scratch);
+        if (e != hipSuccess) return map_err(e);
+        bytes = ci::noalloc_scratch_bytes();
+    }
+    return chol_inverse_batched(dtype, batch, n_uniform, n_dev, offsets_dev, n_max, a, stride_a, x,
+                                stride_x, opts, scratch, bytes, info, stream);
+}
+
 int chol_inverse_backward(int dtype, int64_t batch, int64_t n, const void* x, const void* g,
                           void* ga, int64_t stride, void* stream)
 {
@@ -303,6 +322,8 @@ const char* chol_status_string(int code)
     if (code == 0) return "success";
     if (code == CI_ERR_UNSUPPORTED) return "unsupported combination of arguments";
     if (code == CI_ERR_WORKSPACE) return "workspace too small";
+    if (code == CI_ERR_NOALLOC_LIMIT)
+        return "batch larger than the library-held scratch allows (CI_NOALLOC_MAX_BATCH)";
     if (code <= CI_ERR_LAUNCH && code > CI_ERR_LAUNCH - 1000) {
         std::snprintf(buf, sizeof buf, "HIP launch error %d (%s)", CI_ERR_LAUNCH - code,
                       hipGetErrorString((hipError_t)(CI_ERR_LAUNCH - code)));

@@ -28,4 +28,10 @@ hipError_t launch_varlen(int dtype, int64_t batch, const int32_t* n_dev, const i
                          int n_max, const void* a, void* x, int method, int mixed, int ns_steps,
                          int fill, int32_t* info, void* work, hipStream_t s);
 
+// Device address of the current device's library-held scratch array (taken
+// once per device; the array holds the varlen plan of up to
+// CI_NOALLOC_MAX_BATCH matrices), and its size in bytes.
+hipError_t noalloc_scratch(void** out);
+size_t noalloc_scratch_bytes();
+
 }  // namespace ci

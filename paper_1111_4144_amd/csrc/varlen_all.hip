@@ -1,9 +1,48 @@
 // varlen_all.hip -- the uneven-order batch path for real element types
-// (float, double; orders 1..64).
+// (float, double; orders 1..64), and the library-held scratch array of the
+// allocation-free variant of that path.
+#include <mutex>
+
 #include "varlen_impl.hpp"
 #include "ci_large.hpp"
+#include "cholinv.h"
 
 namespace ci {
+
+// ---- library-held scratch (allocation-free entry point) ---------------------
+// The bucketing plan and the sorted work list of one uneven batch of up to
+// CI_NOALLOC_MAX_BATCH matrices.  Every device the library runs on holds its
+// own copy for the life of the process.  In host code the name `scratch` is
+// only a stand-in: its device address comes from hipGetSymbolAddress, taken
+// once per device with that device current, and only that address is ever
+// passed to a kernel.
+constexpr size_t NOALLOC_SCRATCH_BYTES =
+    varlen_plan_bytes() + ((size_t)CI_NOALLOC_MAX_BATCH * sizeof(int32_t) + 255) / 256 * 256;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[NOALLOC_MAX_DEVICES];
+
+size_t noalloc_scratch_bytes() { return NOALLOC_SCRATCH_BYTES; }
+
+hipError_t noalloc_scratch(void** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 size_t varlen_workspace(int64_t batch)
 {
