@@ -62,3 +62,20 @@ def test_q15_full_batch_sampled():
     wx, we, ws, wi = O.inv_q15(q[idx])
     assert np.array_equal(x[idx], wx) and np.array_equal(xe[idx], we)
     assert np.array_equal(sat[idx], ws) and np.array_equal(info[idx], wi)
+
+
+def test_q15_hand_worked_cases():
+    """The oracle's hand-worked pins on the GPU: an output rounding that meets
+    an exact negative half (2 x 2) and a Y that saturates, which sets the
+    output shift (10 x 10); bit for bit."""
+    q2 = np.zeros((1, 2, 2, 2), np.int16)
+    q2[0, :, :, 0] = [[27752, 21162], [21162, 24209]]
+    x, xe, sat, info = _same(q2)
+    assert x[0, 0, 1, 0] == -12683 and xe[0] == -12
+    n = 10
+    q10 = np.zeros((1, n, n, 2), np.int16)
+    for i in range(n):
+        for j in range(n):
+            q10[0, i, j, 0] = 2048 * (i + 1) if i == j else 2048 * (min(i, j) - 1)
+    x, xe, sat, info = _same(q10)
+    assert sat[0] >= 1 and xe[0] == 4 and x[0, 0, 0, 0] == 16384

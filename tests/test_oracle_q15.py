@@ -98,3 +98,55 @@ def test_q15_saturation_is_counted():
     # the inverse's (1, 1) entry is 1 / r_11^2 (in units of 2^-30 / 2^-30)
     got = O.dequant_q15(x, xe)[0]
     assert abs(got[1, 1].real - (2.0 ** 15 / 181) ** 2) <= 1e-3 * (2.0 ** 15 / 181) ** 2
+
+
+def test_q15_negative_tie_rounds_away_from_zero():
+    """A hand-worked 2 x 2 real case whose output rounding meets an exact
+    negative half, so halves-away-from-zero (-12683) differs from half-up and
+    from half-to-even (both -12682).  a = [[27752, 21162], [21162, 24209]]:
+      r00 = floor(sqrt(27752 * 2^15 = 909377536)) = 30155   (30155^2 = 909324025)
+      r01 = round(21162 * 2^15 / 30155) = round(22995 + 22191/30155) = 22996
+      r11 = floor(sqrt(24209 * 2^15 - 22996^2 = 264464496)) = 16262
+      F   = 2 floor(log2 16262) - ceil(log2 2) = 2 * 13 - 1 = 25
+      t1  = round(2^55 / 16262) = 2215520662831          (remainder 6246)
+      y11 = round(t1 / 16262) = 136239126                (136239125 rem 12081)
+      y01 = round(-22996 * y11 / 30155) = -103895040     (|.| = 103895040 rem 10296)
+      t0  = round(2^55 / 30155) = 1194786835316          (remainder 9988)
+      y00 = round((t0 + 22996 * 103895040) / 30155) = 118851175
+      shift s = 13: round(136239126 / 2^13) = 16631 <= 32767, s = 12 gives 33262
+      x00 = round(118851175 / 8192) = 14508, x11 = 16631,
+      x01 = round(-103895040 / 8192) = round(-12682.5) = -12683, xexp = s - F = -12."""
+    q = np.zeros((1, 2, 2, 2), np.int16)
+    q[0, :, :, 0] = [[27752, 21162], [21162, 24209]]
+    x, xe, sat, info = O.inv_q15(q)
+    assert info[0] == 0 and sat[0] == 0
+    assert xe[0] == -12
+    assert x[0, :, :, 0].tolist() == [[14508, -12683], [-12683, 16631]]
+    assert (x[0, :, :, 1] == 0).all()
+
+
+def test_q15_y_saturation_and_shift_search():
+    """The 10 x 10 matrix A = R^T R with R = (I - N) / 4 (N: ones strictly above
+    the diagonal) has an exact Q15 factor: a_ii = 2048 (i + 1), a_ij =
+    2048 (i - 1) (i < j) in Q15 units, so every radicand is 2^26 and every
+    division exact: r_ii = 8192, r_ij = -8192.  Then F = 2 * 13 - ceil(log2 10)
+    = 22.  The true inverse 16 U^{-1} U^{-T} (U^{-1}_ij = 2^(j-i-1)) has
+    x_00 = 16 (1 + (4^9 - 1)/3) = 1398112, and x_00 2^F = 5.9e12 is beyond the
+    Y range 2^40 - 1, so Y saturates (counted) and the largest |y| is exactly
+    2^40 - 1.  The smallest shift that fits: round((2^40 - 1) / 2^25) = 32768
+    does not fit, s = 26 gives 16384.  So x_00 = 16384 and xexp = 26 - 22 = 4,
+    while the last diagonal entry, y_99 = 2^(F + 30) / 8192^2 = 2^26 (x_99 = 16,
+    exact), gives x_99 = round(2^26 / 2^26) = 1."""
+    n = 10
+    q = np.zeros((1, n, n, 2), np.int16)
+    for i in range(n):
+        for j in range(n):
+            lo = min(i, j)
+            q[0, i, j, 0] = 2048 * (i + 1) if i == j else 2048 * (lo - 1)
+    x, xe, sat, info = O.inv_q15(q)
+    assert info[0] == 0
+    assert sat[0] >= 1
+    assert xe[0] == 4
+    assert x[0, 0, 0, 0] == 16384
+    assert x[0, n - 1, n - 1, 0] == 1
+    assert np.abs(x[0, ..., 0].astype(np.int64)).max() == 16384
