@@ -19,8 +19,10 @@
  *   upper triangle (i <= j) of an input A is read; its strict lower triangle
  *   may hold anything, NaN included.  The imaginary part of a diagonal entry is
  *   ignored.
- * - Calls are asynchronous: they enqueue kernels on `stream` and return.  The
- *   library never synchronises the stream and never allocates device memory on
+ * - Calls are asynchronous: they enqueue kernels on `stream` and return (a
+ *   batch too large for one dispatch grid, whose size counts work-items in 32
+ *   bits, is queued as several launches in order).  The library never
+ *   synchronises the stream and never allocates device memory on
  *   the call path; scratch space is the caller's `work` buffer, sized by
  *   chol_workspace_size().
  *
@@ -240,7 +242,7 @@ int chol_inverse_batched_noalloc(int dtype, int64_t batch, int64_t n_uniform,
  * fill_lower is ignored), then D^{-1} = D^* X_A into x.  The condition number
  * of A is the square of that of D, so the accuracy is that of an inversion
  * at kappa(D)^2.
- *   batch      number of matrices, <= 2^28
+ *   batch      number of matrices
  *   n          order, 0 <= n <= CI_SMALL_NMAX
  *   d, stride  device input, matrix b at d + b*stride, leading dimension n
  *              (stride >= n*n; ignored when batch == 1); not modified
@@ -284,7 +286,7 @@ int chol_inverse_backward(int dtype, int64_t batch, int64_t n, const void* x, co
  *   - the output is int16 (re, im) mantissas x with X = x 2^xexp (xexp per
  *     matrix, the smallest shift that fits), written in full with x_ji =
  *     conj(x_ij).
- *   batch        number of matrices (<= 2^36)
+ *   batch        number of matrices
  *   n            order, 0 <= n <= CI_Q15_NMAX
  *   a, stride    device int16, matrix b at a + 2*b*stride (stride in complex
  *                entries, >= n*n; ignored when batch == 1), leading dimension n
@@ -339,7 +341,10 @@ const char* chol_version(void);
  * For orders up to 16 several kernels can invert a uniform batch (engines:
  * 1 one lane per matrix, direct loads; 2 the same with LDS staging; 3 with
  * persistent staging; 4 sixteen-lane groups; 5 sixteen-lane groups with the
- * Newton-Schulz step on MFMA, mixed precision only).  The choice depends on
+ * Newton-Schulz step on MFMA, mixed precision only; 6 four-lane groups with
+ * sixteen matrices per wave, orders 9..16, CI_F32 / CI_C64, the refinement
+ * on MFMA, the built-in choice for CI_C64 orders 9..16 and for CI_F32 orders
+ * 9..16 in mixed precision).  The choice depends on
  * the device, so it is measured, not fixed.
  *
  * chol_autotune times every candidate engine of (dtype, opts) for each order
@@ -361,6 +366,13 @@ int chol_autotune(int dtype, const ci_opts* opts, int n_lo, int n_hi, int64_t ba
 /* The recorded engine for (dtype, opts precision/method, order n); 0 when
  * the built-in choice applies.  Negative for an invalid argument. */
 int chol_tuned_engine(int dtype, const ci_opts* opts, int n);
+
+/* Record `engine` (one of the candidates above for this dtype, precision and
+ * order, or 0 for the built-in choice) for (dtype, opts precision/method,
+ * order n, 1..16) without measuring, e.g. a choice read from a tuning file or
+ * one a test wants to exercise.  Returns 0, or -k for an invalid argument k
+ * (-4: the engine cannot invert this combination). */
+int chol_tune_set(int dtype, const ci_opts* opts, int n, int engine);
 
 /* Forget every recorded choice. */
 void chol_autotune_clear(void);

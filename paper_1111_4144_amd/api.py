@@ -11,7 +11,7 @@ on the GPU.  Calls are asynchronous on torch's current stream unless
 * ``factor(A)`` / ``ldl(A)``                    Section II / II.A factorisations
 * ``inverse_backward(X, G)``                    gA = -X Gh X
 * ``CholInverse``                               autograd.Function saving X
-* ``autotune`` / ``tuned_engine`` / ``autotune_clear``  engine choice per order
+* ``autotune`` / ``tuned_engine`` / ``tune_set`` / ``autotune_clear``  engine choice per order
 """
 from __future__ import annotations
 
@@ -351,6 +351,13 @@ def tuned_engine(dtype, n, *, method="chol", precision="plain") -> int:
     if rc < 0:
         L.check("chol_tuned_engine", rc)
     return int(rc)
+
+
+def tune_set(dtype, n, engine, *, method="chol", precision="plain") -> None:
+    """Record ``engine`` for order n without measuring (0 = built-in choice)."""
+    opts = L.make_opts(method, precision, 0, True)
+    L.check("chol_tune_set", L.lib().chol_tune_set(_code_of(dtype), ctypes.byref(opts), int(n),
+                                                   int(engine)))
 
 
 def autotune_clear() -> None:

@@ -50,8 +50,8 @@ int check_opts(const ci_opts& o, int dtype)
     return 0;
 }
 
-hipError_t run_small(int dtype, int64_t n, int op, int method, int mixed, const ci::BatchArgs& p,
-                     hipStream_t s)
+hipError_t run_small_one(int dtype, int64_t n, int op, int method, int mixed,
+                         const ci::BatchArgs& p, hipStream_t s)
 {
     if (op == ci::OP_INV) {
         const int eng = ci::tuned_engine(dtype, mixed, method, (int)n);
@@ -60,6 +60,30 @@ hipError_t run_small(int dtype, int64_t n, int op, int method, int mixed, const 
     }
     if (n <= ci::tpm_nmax(dtype, mixed)) return ci::launch_tpm(dtype, (int)n, op, method, mixed, p, s);
     return ci::launch_group(dtype, (int)n, op, method, mixed, p, s);
+}
+
+// A dispatch's grid counts work-items in 32 bits.  The batched kernels use at
+// most 256 lanes per matrix, so batches are launched in pieces of at most
+// 2^22 matrices (2^30 work-items).
+constexpr int64_t SMALL_CHUNK = (int64_t)1 << 22;
+
+hipError_t run_small(int dtype, int64_t n, int op, int method, int mixed, const ci::BatchArgs& p,
+                     hipStream_t s)
+{
+    if (p.batch <= SMALL_CHUNK) return run_small_one(dtype, n, op, method, mixed, p, s);
+    const size_t es = elem_size(dtype);
+    const size_t rs = (dtype == CI_F32 || dtype == CI_C64) ? 4 : 8;   // LDL pivot type
+    for (int64_t b0 = 0; b0 < p.batch; b0 += SMALL_CHUNK) {
+        ci::BatchArgs q = p;
+        q.batch = std::min(SMALL_CHUNK, p.batch - b0);
+        q.a = static_cast<const char*>(p.a) + (size_t)(b0 * p.sa) * es;
+        q.x = static_cast<char*>(p.x) + (size_t)(b0 * p.sx) * es;
+        q.info = p.info ? p.info + b0 : nullptr;
+        q.dout = p.dout ? static_cast<char*>(p.dout) + (size_t)(b0 * n) * rs : nullptr;
+        const hipError_t e = run_small_one(dtype, n, op, method, mixed, q, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace
@@ -128,12 +152,23 @@ int chol_solve(int dtype, int method, int64_t batch, int64_t n, int64_t nrhs, co
     if (batch > 1 && stride_x < ldx * n) return -15;
     if (x == b && (ldx != ldb || (batch > 1 && stride_x != stride_b))) return -13;
     if (!work) return 0;
-    // one lane per right-hand side; the grid (32-lane blocks at the least)
-    // must stay below 2^32 blocks
-    if (batch > ((int64_t)1 << 36) / nrhs) return -5;
-    ci::SolveArgs p{r, ldr, batch > 1 ? stride_r : 0, d, b, ldb, batch > 1 ? stride_b : 0,
-                    x, ldx, batch > 1 ? stride_x : 0, batch, (int)n, (int)nrhs};
-    return map_err(ci::launch_solve(dtype, method, p, (hipStream_t)stream));
+    // one lane per right-hand side: pieces of at most 2^30 right-hand sides
+    // per launch (the grid counts work-items in 32 bits)
+    const int64_t chunk = std::max<int64_t>(1, ((int64_t)1 << 30) / nrhs);
+    const size_t es = elem_size(dtype), rs = (dtype == CI_F32 || dtype == CI_C64) ? 4 : 8;
+    for (int64_t b0 = 0; b0 < batch; b0 += chunk) {
+        const int64_t cnt = std::min(chunk, batch - b0);
+        const int64_t sr = batch > 1 ? stride_r : 0, sb = batch > 1 ? stride_b : 0,
+                      sx = batch > 1 ? stride_x : 0;
+        ci::SolveArgs p{static_cast<const char*>(r) + (size_t)(b0 * sr) * es, ldr, sr,
+                        d ? static_cast<const char*>(d) + (size_t)(b0 * n) * rs : nullptr,
+                        static_cast<const char*>(b) + (size_t)(b0 * sb) * es, ldb, sb,
+                        static_cast<char*>(x) + (size_t)(b0 * sx) * es, ldx, sx, cnt, (int)n,
+                        (int)nrhs};
+        const int rc = map_err(ci::launch_solve(dtype, method, p, (hipStream_t)stream));
+        if (rc) return rc;
+    }
+    return 0;
 }
 
 int chol_inverse_nonherm(int dtype, int64_t batch, int64_t n, const void* d, int64_t stride,
@@ -141,7 +176,7 @@ int chol_inverse_nonherm(int dtype, int64_t batch, int64_t n, const void* d, int
                          int32_t* info, void* stream)
 {
     if (!valid_dtype(dtype)) return -1;
-    if (batch < 0 || batch > ((int64_t)1 << 28)) return -2;
+    if (batch < 0) return -2;
     if (n < 0 || n > CI_SMALL_NMAX) return -3;
     if (batch > 0 && n > 0 && !d) return -4;
     if (batch > 1 && stride < n * n) return -5;
@@ -155,21 +190,33 @@ int chol_inverse_nonherm(int dtype, int64_t batch, int64_t n, const void* d, int
     if (work_bytes < need || !work) return CI_ERR_WORKSPACE;
     const int64_t nn = n * n;
     const int64_t sd = batch > 1 ? stride : nn;
-    void* a = work;
-    void* xa = (char*)work + need / 2;
-    hipError_t e = ci::launch_gram(dtype, d, sd, a, batch, (int)n, s);
-    if (e != hipSuccess) return map_err(e);
-    // X_A = (D D^*)^{-1}, written in full (both halves feed the product)
-    ci::BatchArgs p{a, xa, batch, n, nn, n, nn, o.ns_steps, 1, info, nullptr};
-    e = run_small(dtype, n, ci::OP_INV, o.method, o.precision == CI_MIXED, p, s);
-    if (e != hipSuccess) return map_err(e);
-    return map_err(ci::launch_adjoint_product(dtype, d, sd, xa, x, sd, batch, (int)n, s));
+    const size_t es = elem_size(dtype);
+    // one lane per entry in the product kernels: pieces of 2^18 matrices
+    // (at most 2^30 work-items at order 64)
+    constexpr int64_t chunk = (int64_t)1 << 18;
+    for (int64_t b0 = 0; b0 < batch; b0 += chunk) {
+        const int64_t cnt = std::min(chunk, batch - b0);
+        const void* dc = static_cast<const char*>(d) + (size_t)(b0 * sd) * es;
+        void* xc = static_cast<char*>(x) + (size_t)(b0 * sd) * es;
+        void* a = static_cast<char*>(work) + (size_t)(b0 * nn) * es;
+        void* xa = static_cast<char*>(work) + need / 2 + (size_t)(b0 * nn) * es;
+        hipError_t e = ci::launch_gram(dtype, dc, sd, a, cnt, (int)n, s);
+        if (e != hipSuccess) return map_err(e);
+        // X_A = (D D^*)^{-1}, written in full (both halves feed the product)
+        ci::BatchArgs p{a, xa, cnt, n, nn, n, nn, o.ns_steps, 1, info ? info + b0 : nullptr,
+                        nullptr};
+        e = run_small(dtype, n, ci::OP_INV, o.method, o.precision == CI_MIXED, p, s);
+        if (e != hipSuccess) return map_err(e);
+        e = ci::launch_adjoint_product(dtype, dc, sd, xa, xc, sd, cnt, (int)n, s);
+        if (e != hipSuccess) return map_err(e);
+    }
+    return 0;
 }
 
 int chol_inverse_q15(int64_t batch, int64_t n, const int16_t* a, int64_t stride, int16_t* x,
                      int32_t* xexp, int32_t* sat, int32_t* info, void* stream)
 {
-    if (batch < 0 || batch > ((int64_t)1 << 36)) return -1;
+    if (batch < 0) return -1;
     if (n < 0 || n > CI_Q15_NMAX) return -2;
     const bool work = batch > 0 && n > 0;
     if (work && !a) return -3;
@@ -177,8 +224,18 @@ int chol_inverse_q15(int64_t batch, int64_t n, const int16_t* a, int64_t stride,
     if (work && (!x || x == a)) return -5;
     if (work && !xexp) return -6;
     if (!work) return (batch > 0 && info) ? map_err(ci::fill_i32(info, batch, 0, (hipStream_t)stream)) : 0;
-    return map_err(ci::launch_inv_q15(a, batch > 1 ? stride : n * n, x, xexp, sat, info, batch,
-                                      (int)n, (hipStream_t)stream));
+    // one lane per matrix: pieces of 2^30 matrices per launch
+    const int64_t st = batch > 1 ? stride : n * n;
+    constexpr int64_t chunk = (int64_t)1 << 30;
+    for (int64_t b0 = 0; b0 < batch; b0 += chunk) {
+        const int64_t cnt = std::min(chunk, batch - b0);
+        const int rc = map_err(ci::launch_inv_q15(a + 2 * b0 * st, st, x + 2 * b0 * st, xexp + b0,
+                                                  sat ? sat + b0 : nullptr,
+                                                  info ? info + b0 : nullptr, cnt, (int)n,
+                                                  (hipStream_t)stream));
+        if (rc) return rc;
+    }
+    return 0;
 }
 
 int chol_inverse_compare(int dtype, int variant, int method, int64_t batch, int64_t n,
@@ -187,7 +244,7 @@ int chol_inverse_compare(int dtype, int variant, int method, int64_t batch, int6
     if (!valid_dtype(dtype)) return -1;
     if (variant != CI_III_A && variant != CI_III_B) return -2;
     if (method != CI_METHOD_CHOL && (method != CI_METHOD_LDL || variant != CI_III_A)) return -3;
-    if (batch < 0 || batch > ((int64_t)1 << 36)) return -4;
+    if (batch < 0) return -4;
     if (n < 0 || n > CI_COMPARE_NMAX) return -5;
     const bool work = batch > 0 && n > 0;
     if (work && !a) return -6;
@@ -197,7 +254,17 @@ int chol_inverse_compare(int dtype, int variant, int method, int64_t batch, int6
     if (!work) return (batch > 0 && info) ? map_err(ci::fill_i32(info, batch, 0, s)) : 0;
     const int k = variant == CI_III_B ? 2 : (method == CI_METHOD_LDL ? 1 : 0);
     const int64_t st = batch > 1 ? stride : n * n;
-    return map_err(ci::launch_compare(dtype, k, a, st, x, st, info, batch, (int)n, s));
+    const size_t es = elem_size(dtype);
+    constexpr int64_t chunk = (int64_t)1 << 30;          // one lane per matrix
+    for (int64_t b0 = 0; b0 < batch; b0 += chunk) {
+        const int64_t cnt = std::min(chunk, batch - b0);
+        const int rc = map_err(ci::launch_compare(
+            dtype, k, static_cast<const char*>(a) + (size_t)(b0 * st) * es, st,
+            static_cast<char*>(x) + (size_t)(b0 * st) * es, st, info ? info + b0 : nullptr, cnt,
+            (int)n, s));
+        if (rc) return rc;
+    }
+    return 0;
 }
 
 int chol_inverse(int dtype, int64_t n, const void* a, int64_t lda, void* x, int64_t ldx,
@@ -289,7 +356,16 @@ int chol_inverse_backward(int dtype, int64_t batch, int64_t n, const void* x, co
     if (batch > 0 && n > 0 && !ga) return -6;
     if (stride < n * n) return -7;
     if (batch == 0 || n == 0) return 0;
-    return map_err(ci::launch_backward(dtype, (int)n, x, g, ga, batch, stride, (hipStream_t)stream));
+    const size_t es = elem_size(dtype);
+    for (int64_t b0 = 0; b0 < batch; b0 += SMALL_CHUNK) {
+        const int64_t cnt = std::min(SMALL_CHUNK, batch - b0);
+        const size_t off = (size_t)(b0 * stride) * es;
+        const int rc = map_err(ci::launch_backward(
+            dtype, (int)n, static_cast<const char*>(x) + off, static_cast<const char*>(g) + off,
+            static_cast<char*>(ga) + off, cnt, stride, (hipStream_t)stream));
+        if (rc) return rc;
+    }
+    return 0;
 }
 
 size_t chol_workspace_size(int fn, int dtype, int64_t batch, int64_t n, const ci_opts* opts)
@@ -358,6 +434,17 @@ int chol_tuned_engine(int dtype, const ci_opts* opts, int n)
     if (check_opts(o, dtype)) return -2;
     if (n < 0 || n > CI_SMALL_NMAX) return -3;
     return ci::tuned_engine(dtype, o.precision == CI_MIXED, o.method, n);
+}
+
+int chol_tune_set(int dtype, const ci_opts* opts, int n, int engine)
+{
+    if (!valid_dtype(dtype)) return -1;
+    ci_opts o = opts ? *opts : default_opts();
+    if (check_opts(o, dtype)) return -2;
+    if (n < 1 || n > 16) return -3;
+    if (!ci::engine_valid(dtype, o.precision == CI_MIXED, n, engine)) return -4;
+    ci::tune_set(dtype, o.precision == CI_MIXED, o.method, n, engine);
+    return 0;
 }
 
 void chol_autotune_clear(void) { ci::autotune_clear(); }

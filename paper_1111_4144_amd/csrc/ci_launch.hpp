@@ -52,7 +52,8 @@ enum {
     ENG_TPM_STAGED = 2,
     ENG_TPM_PERSIST = 3,
     ENG_GROUP_LANES = 4,
-    ENG_GROUP_MFMA = 5
+    ENG_GROUP_MFMA = 5,
+    ENG_QUAD16 = 6
 };
 // Recorded choice for (dtype, mixed, method, n), ENG_DEFAULT if none.
 int tuned_engine(int dtype, int mixed, int method, int n);
@@ -63,6 +64,10 @@ hipError_t launch_engine(int engine, int dtype, int n, int op, int method, int m
 int autotune(int dtype, int mixed, int method, int ns_steps, int n_lo, int n_hi, int64_t batch,
              const char* cache_path, hipStream_t s);
 void autotune_clear();
+// Whether `engine` can invert (dtype, mixed, order n) (ENG_DEFAULT always can),
+// and recording a choice made by the caller.
+bool engine_valid(int dtype, int mixed, int n, int engine);
+void tune_set(int dtype, int mixed, int method, int n, int engine);
 
 int tpm_nmax(int dtype, int mixed);
 
@@ -88,6 +93,10 @@ hipError_t launch_group_f32(int n, int op, int method, int mixed, const BatchArg
 hipError_t launch_group_f64(int n, int op, int method, int mixed, const BatchArgs& p, hipStream_t s);
 hipError_t launch_group_c64(int n, int op, int method, int mixed, const BatchArgs& p, hipStream_t s);
 hipError_t launch_group_c128(int n, int op, int method, int mixed, const BatchArgs& p, hipStream_t s);
+// Four lanes per matrix, sixteen matrices per wave (orders <= 16, float and
+// complex float, inversion only; mixed precision refines on MFMA).
+hipError_t launch_quad16(int dtype, int n, int op, int method, int mixed, const BatchArgs& p,
+                         hipStream_t s);
 // LDS-resident group kernels for orders 17..64 (real) / 17..32 (complex).
 hipError_t launch_wpm_f32(int n, int op, int method, int mixed, const BatchArgs& p, hipStream_t s);
 hipError_t launch_wpm_f64(int n, int op, int method, int mixed, const BatchArgs& p, hipStream_t s);

@@ -168,6 +168,10 @@ CI_D T row_sum16(T v)
     v += dpp_f<0x140>(v);   // row_mirror
     return v;
 }
+CI_D float quad_sumv(float v) { return quad_sum<4>(v); }
+CI_D double quad_sumv(double v) { return quad_sum<4>(v); }
+CI_D cf quad_sumv(cf v) { return cf{quad_sum<4>(v.re), quad_sum<4>(v.im)}; }
+CI_D cd quad_sumv(cd v) { return cd{quad_sum<4>(v.re), quad_sum<4>(v.im)}; }
 CI_D float row_sum16v(float v) { return row_sum16(v); }
 CI_D double row_sum16v(double v) { return row_sum16(v); }
 CI_D cf row_sum16v(cf v) { return cf{row_sum16(v.re), row_sum16(v.im)}; }
@@ -273,8 +277,10 @@ CI_D int group_core(V (&M)[S][NB], P (&piv)[S], typename vt<V>::real (&dall)[NB]
                 const V rik = bc<G>(src, k % G);
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
-                    msub(acc[s], rik, M[s][k]);
-                    opaque(acc[s]);
+                    if (s * G + G - 1 > i) {          // a column j > i in this slot
+                        msub(acc[s], rik, M[s][k]);
+                        opaque(acc[s]);
+                    }
                 }
             }
             V xnew[S];
@@ -296,6 +302,19 @@ CI_D int group_core(V (&M)[S][NB], P (&piv)[S], typename vt<V>::real (&dall)[NB]
                 madd(prod, M[0][i], cj(xnew[0]));
                 prod = (q > i) ? prod : mk<V>(R(0));
                 d = add(d, neg(row_sum16v(prod)));
+            } else if constexpr (G == 4) {
+                // the same with four columns per lane: local products over the
+                // lane's columns k > i, then a sum over the quad
+                V prod = mk<V>(R(0));
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    if (s * G + G - 1 > i) {
+                        V t = mk<V>(R(0));
+                        madd(t, M[s][i], cj(xnew[s]));
+                        prod = add(prod, (s * G + q > i) ? t : mk<V>(R(0)));
+                    }
+                }
+                d = add(d, neg(quad_sumv(prod)));
             } else {
 #pragma unroll
                 for (int k = i + 1; k < NB; ++k) {

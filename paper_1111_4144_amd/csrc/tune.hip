@@ -2,9 +2,10 @@
 //
 // For orders up to 16 several kernels can invert a batch: the one-lane-per-
 // matrix kernels with direct loads, one-shot LDS staging or persistent
-// staging (orders up to the per-type register limit), and the 16-lane group
+// staging (orders up to the per-type register limit), the 16-lane group
 // kernels with the Newton-Schulz step on the lane groups or on MFMA (mixed
-// precision).  chol_autotune times every candidate for each order of a range
+// precision), and the 4-lane groups with sixteen matrices per wave (orders
+// 9..16, float and complex float).  chol_autotune times every candidate for each order of a range
 // on a synthetic batch on the caller's device and stream and records the
 // fastest; run_small consults the record.  Choices can be persisted in a text
 // cache keyed by the device (name and compute-unit count), so later processes
@@ -82,6 +83,7 @@ int candidates(int dtype, int mixed, int n, int* out)
     if (n <= 16) {
         out[k++] = ENG_GROUP_LANES;
         if (mixed && (dtype == DT_F32 || dtype == DT_C64)) out[k++] = ENG_GROUP_MFMA;
+        if (n >= 9 && (dtype == DT_F32 || dtype == DT_C64)) out[k++] = ENG_QUAD16;
     }
     return k;
 }
@@ -101,7 +103,7 @@ bool load_cache(const char* path, const std::string& dev, int dtype, int mixed, 
             continue;
         if (dev != dname || d != dtype || p != mixed || m != method || n < n_lo || n > n_hi)
             continue;
-        if (e < ENG_DEFAULT || e > ENG_GROUP_MFMA) continue;
+        if (e < ENG_DEFAULT || e > ENG_QUAD16) continue;
         g_table[dtype][mixed][method][n] = e;
         have[n] = true;
     }
@@ -128,6 +130,7 @@ hipError_t launch_engine(int engine, int dtype, int n, int op, int method, int m
     case ENG_TPM_PERSIST: p.variant = VARIANT_PERSIST; return launch_tpm(dtype, n, op, method, mixed, p, s);
     case ENG_GROUP_LANES: p.ns_engine = NS_ENGINE_LANES; return launch_group(dtype, n, op, method, mixed, p, s);
     case ENG_GROUP_MFMA: p.ns_engine = NS_ENGINE_MFMA; return launch_group(dtype, n, op, method, mixed, p, s);
+    case ENG_QUAD16: return launch_quad16(dtype, n, op, method, mixed, p, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -200,6 +203,22 @@ int autotune(int dtype, int mixed, int method, int ns_steps, int n_lo, int n_hi,
     (void)hipFree(x);
     (void)hipFree(info);
     return err == hipSuccess ? measured : -1000 - (int)err;
+}
+
+bool engine_valid(int dtype, int mixed, int n, int engine)
+{
+    if (engine == ENG_DEFAULT) return true;
+    int cand[8];
+    const int nc = candidates(dtype, mixed, n, cand);
+    for (int c = 0; c < nc; ++c)
+        if (cand[c] == engine) return true;
+    return false;
+}
+
+void tune_set(int dtype, int mixed, int method, int n, int engine)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_table[dtype][mixed ? 1 : 0][method ? 1 : 0][n] = engine;
 }
 
 void autotune_clear()

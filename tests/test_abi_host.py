@@ -105,3 +105,23 @@ def test_argument_validation_codes():
 def test_workspace_sizes_are_host_only():
     L, lib = _lib()
     assert lib.chol_workspace_size(L.CI_FN_BATCHED, 2, 1000, 8, None) == 0
+
+
+def test_tune_set_validates_engines():
+    """chol_tune_set records only engines that can invert the combination (no
+    GPU work: the table is host-side)."""
+    L, lib = _lib()
+    mixed = L.make_opts("chol", "mixed", 1)
+    plain = L.make_opts()
+    try:
+        assert lib.chol_tune_set(L.CI_C64, ctypes.byref(mixed), 16, 6) == 0
+        assert lib.chol_tuned_engine(L.CI_C64, ctypes.byref(mixed), 16) == 6
+        assert lib.chol_tune_set(L.CI_C64, ctypes.byref(mixed), 16, 0) == 0
+        assert lib.chol_tune_set(L.CI_C128, ctypes.byref(plain), 16, 6) == -4   # complex128
+        assert lib.chol_tune_set(L.CI_C64, ctypes.byref(mixed), 8, 6) == -4     # order < 9
+        assert lib.chol_tune_set(L.CI_C64, ctypes.byref(plain), 16, 5) == -4    # MFMA needs mixed
+        assert lib.chol_tune_set(L.CI_C64, ctypes.byref(mixed), 16, 9) == -4    # no such engine
+        assert lib.chol_tune_set(L.CI_C64, ctypes.byref(mixed), 17, 4) == -3
+        assert lib.chol_tune_set(7, ctypes.byref(mixed), 16, 4) == -1
+    finally:
+        lib.chol_autotune_clear()
