@@ -191,7 +191,7 @@ FP32_MFMA_PEAK = 157.3e12
 FP64_MFMA_PEAK = 78.6e12
 
 
-def large_workloads(torch, api, G, dev, steps):
+def large_workloads(torch, api, G, dev, steps, tune=True):
     """Single large SPD matrices, A = Q diag(lambda) Q^T, lambda log-spaced over
     [1, 1e6], at N = 4096 and 8192: FP32 + FP64 pivots (factor + inverse, and
     with one Newton-Schulz step) and plain FP64.  Rates use the nominal N^3
@@ -215,6 +215,11 @@ def large_workloads(torch, api, G, dev, steps):
             A = torch.from_numpy(a).to(dev).to(dt)
             X = torch.empty_like(A)
             a_in = A.cpu().numpy().astype(np.float64)
+            # configuration of the blocked path (diagonal kernel, inverse form,
+            # split-K target) measured on this device for this order
+            if tune:
+                api.autotune(dt, precision=prec, orders=(n, n))
+            out[tag + "_config"] = api.tuned_engine(dt, n, precision=prec)
             for ns in ns_list:
                 st = {}
                 step_ms, _ = _time_loop(
@@ -246,7 +251,7 @@ def large_workloads(torch, api, G, dev, steps):
     return out
 
 
-def varlen_workload(torch, api, G, dev, steps):
+def varlen_workload(torch, api, G, dev, steps, tune=True):
     """262,144 real FP32 SPD matrices of orders U{2..64} in one packed buffer,
     one persistent launch (device bucketing prologue included), eager and as a
     replayed graph.  Bytes: A in + X out = 8 N^2 per matrix."""
@@ -256,6 +261,8 @@ def varlen_workload(torch, api, G, dev, steps):
     OF = torch.from_numpy(offsets).to(dev)
     XV = torch.empty_like(P)
     ws = torch.empty(api.varlen_workspace_bytes(P, S.shape[0]), dtype=torch.uint8, device=dev)
+    # edge of the last size bucket, measured on this batch
+    edge = api.autotune_varlen(P, S, OF, n_max=64, workspace=ws) if tune else 33
 
     def call():
         api.inverse_varlen(P, S, OF, n_max=64, out=XV, workspace=ws)
@@ -286,7 +293,7 @@ def varlen_workload(torch, api, G, dev, steps):
     return {"varlen_eager_mat_per_s": count / (e_ms / 1e3),
             "varlen_graph_mat_per_s": count / (g_ms / 1e3),
             "varlen_graph_hbm_frac": nbytes / (g_ms / 1e3) / HBM_PEAK,
-            "varlen_graph_ms": g_ms,
+            "varlen_graph_ms": g_ms, "varlen_bucket_edge": edge,
             "varlen_sampled_max_rel_err_vs_lapack": worst}
 
 
@@ -439,8 +446,10 @@ def main():
     from paper_1111_4144_amd import api, inputs as G
 
     if args.only:
-        fn = {"large": lambda: large_workloads(torch, api, G, dev, max(2, args.steps // 4)),
-              "varlen": lambda: varlen_workload(torch, api, G, dev, max(3, args.steps // 2))}
+        fn = {"large": lambda: large_workloads(torch, api, G, dev, max(2, args.steps // 4),
+                                               not args.no_tune),
+              "varlen": lambda: varlen_workload(torch, api, G, dev, max(3, args.steps // 2),
+                                                not args.no_tune)}
         print(json.dumps({"only": args.only, "details": fn[args.only]()}), flush=True)
         return
 
@@ -583,9 +592,11 @@ def main():
         details.update(q15_workload(torch, api, G, dev, max(3, args.steps // 2)))
         details.update(compare_workload(torch, api, a8, A8, max(3, args.steps // 4)))
     if not args.no_extras and not args.no_large:
-        details.update(large_workloads(torch, api, G, dev, max(2, args.steps // 4)))
+        details.update(large_workloads(torch, api, G, dev, max(2, args.steps // 4),
+                                       not args.no_tune))
     if not args.no_extras:
-        details.update(varlen_workload(torch, api, G, dev, max(3, args.steps // 2)))
+        details.update(varlen_workload(torch, api, G, dev, max(3, args.steps // 2),
+                                       not args.no_tune))
         details.update(plain_small_workload(torch, api, G, dev, max(3, args.steps // 2)))
 
     line = {

@@ -170,8 +170,8 @@ int chol_solve(int dtype, int method, int64_t batch, int64_t n, int64_t nrhs, co
  * the inverse of R by block columns and the upper half of X = R^{-1} R^{-T}
  * as one MFMA product (the same n^3/2 multiplies as Section IV, reading
  * "zero-skipping triangular inverse"; the block form of the Section IV
- * recurrence itself is selected by the environment variable
- * CHOLINV_LARGE_INVERSE=blocked_iv), then the Newton-Schulz steps as an FP64
+ * recurrence itself is large-order configuration 4, see the tuner below),
+ * then the Newton-Schulz steps as an FP64
  * and an FP32 MFMA product.  There only CI_METHOD_CHOL and real types
  * (CI_F32, CI_F64) are supported (else CI_ERR_UNSUPPORTED), x must not equal
  * a, and X is always written in full (fill_lower is ignored).
@@ -261,8 +261,10 @@ int chol_inverse_nonherm(int dtype, int64_t batch, int64_t n, const void* d, int
  * L = Re<G, X> restricted to Hermitian A:  gA = -X Gh X, Gh = (G + G^H)/2.
  * It reuses the forward's X (full Hermitian, e.g. written with fill_lower = 1)
  * instead of recomputing the inverse.  gA is Hermitian and written in full.
- *   x, g, ga    device, batch matrices of order n (<= CI_SMALL_NMAX), leading
- *               dimension n, matrix b at ptr + b*stride
+ *   x, g, ga    device, batch matrices of order n (<= CI_SMALL_NMAX; CI_C128
+ *               only up to 32, larger orders give CI_ERR_UNSUPPORTED: three
+ *               64 x 64 complex128 matrices do not fit one workgroup's LDS),
+ *               leading dimension n, matrix b at ptr + b*stride
  */
 int chol_inverse_backward(int dtype, int64_t batch, int64_t n, const void* x, const void* g,
                           void* ga, int64_t stride, void* stream);
@@ -348,7 +350,8 @@ const char* chol_version(void);
  * the device, so it is measured, not fixed.
  *
  * chol_autotune times every candidate engine of (dtype, opts) for each order
- * n_lo..n_hi (1 <= n_lo <= n_hi <= 16) on a synthetic batch of `batch`
+ * n_lo..n_hi (1 <= n_lo <= n_hi <= 16; n_lo == n_hi > CI_SMALL_NMAX tunes a
+ * large order instead, see below) on a synthetic batch of `batch`
  * diagonally dominant matrices on `stream`, and records the fastest (ties
  * within 1% go to the lower engine number).  Later chol_inverse /
  * chol_inverse_batched calls with the same dtype, precision and method use the
@@ -364,15 +367,44 @@ int chol_autotune(int dtype, const ci_opts* opts, int n_lo, int n_hi, int64_t ba
                   const char* cache_path, void* stream);
 
 /* The recorded engine for (dtype, opts precision/method, order n); 0 when
- * the built-in choice applies.  Negative for an invalid argument. */
+ * the built-in choice applies.  n > CI_SMALL_NMAX: the large-order
+ * configuration recorded for n's power-of-two bucket (large orders, below);
+ * n = 0: the uneven-batch bucket edge (see chol_autotune_varlen).
+ * Negative for an invalid argument. */
 int chol_tuned_engine(int dtype, const ci_opts* opts, int n);
 
 /* Record `engine` (one of the candidates above for this dtype, precision and
  * order, or 0 for the built-in choice) for (dtype, opts precision/method,
  * order n, 1..16) without measuring, e.g. a choice read from a tuning file or
- * one a test wants to exercise.  Returns 0, or -k for an invalid argument k
- * (-4: the engine cannot invert this combination). */
+ * one a test wants to exercise.  n > CI_SMALL_NMAX records a large-order
+ * configuration 0..4 for n's bucket; n = 0 records the uneven-batch bucket
+ * edge (0, 17, 25 or 33).  Returns 0, or -k for an invalid argument k (-4:
+ * the engine cannot invert this combination). */
 int chol_tune_set(int dtype, const ci_opts* opts, int n, int engine);
+
+/* ---- large orders (n > CI_SMALL_NMAX, real types, Cholesky) -------------
+ * chol_autotune with n_lo == n_hi == n > CI_SMALL_NMAX times the large-order
+ * configurations on a synthetic symmetric positive-definite matrix of order
+ * n and records the fastest for n's power-of-two bucket (batch is ignored;
+ * the cache file and the tie rule are those above).  Configurations:
+ *   0 diagonal blocks sub-blocked on MFMA, blocked triangular inverse and
+ *     X = M M^T, split-K products aiming at 512 workgroups (built-in)
+ *   1, 2 the same aiming at 256 / 1024 workgroups
+ *   3 diagonal blocks by the row-by-row Crout recurrence
+ *   4 the Section IV recurrence in block form for the inverse
+ * Returns 1 when it measured, 0 when the cache had the answer.  Later
+ * chol_inverse / chol_factor calls of that bucket use the record. */
+
+/* ---- uneven batches ----------------------------------------------------------
+ * chol_autotune_varlen times the uneven-batch path on the caller's own batch
+ * (arguments as chol_inverse_batched with n_uniform = 0; x is overwritten
+ * with the inverses) for three edges of its last size bucket, whose orders
+ * are inverted by four waves per matrix: 33 (built-in), 25 and 17, and
+ * records the fastest for (dtype, precision, method).  Real types only.
+ * Returns the chosen edge, or a negative code. */
+int chol_autotune_varlen(int dtype, const ci_opts* opts, int64_t batch, const int32_t* n_dev,
+                         const int64_t* offsets_dev, int64_t n_max, const void* a, void* x,
+                         void* work, size_t work_bytes, void* stream);
 
 /* Forget every recorded choice. */
 void chol_autotune_clear(void);

@@ -29,7 +29,8 @@ EXPORTS = ("chol_factor", "ldl_factor", "chol_solve", "chol_inverse", "chol_inve
            "chol_inverse_batched_noalloc", "chol_inverse_nonherm", "chol_inverse_q15", "chol_inverse_compare",
            "chol_inverse_backward", "chol_workspace_size",
            "chol_status_string", "chol_version",
-           "chol_autotune", "chol_tuned_engine", "chol_tune_set", "chol_autotune_clear")
+           "chol_autotune", "chol_tuned_engine", "chol_tune_set", "chol_autotune_varlen",
+           "chol_autotune_clear")
 
 
 class ci_opts(ctypes.Structure):
@@ -82,6 +83,9 @@ def lib():
     L.chol_autotune.argtypes = [_i32, ctypes.POINTER(ci_opts), _i32, _i32, _i64, ctypes.c_char_p, _vp]
     L.chol_tuned_engine.argtypes = [_i32, ctypes.POINTER(ci_opts), _i32]
     L.chol_tune_set.argtypes = [_i32, ctypes.POINTER(ci_opts), _i32, _i32]
+    L.chol_autotune_varlen.argtypes = [_i32, ctypes.POINTER(ci_opts), _i64, _vp, _vp, _i64, _vp,
+                                       _vp, _vp, _sz, _vp]
+    L.chol_autotune_varlen.restype = _i32
     L.chol_tune_set.restype = _i32
     L.chol_autotune_clear.argtypes = []
     L.chol_autotune_clear.restype = None

@@ -11,7 +11,8 @@ on the GPU.  Calls are asynchronous on torch's current stream unless
 * ``factor(A)`` / ``ldl(A)``                    Section II / II.A factorisations
 * ``inverse_backward(X, G)``                    gA = -X Gh X
 * ``CholInverse``                               autograd.Function saving X
-* ``autotune`` / ``tuned_engine`` / ``tune_set`` / ``autotune_clear``  engine choice per order
+* ``autotune`` / ``autotune_varlen`` / ``tuned_engine`` / ``tune_set`` / ``autotune_clear``
+  engine choice per order, large-order configuration, uneven-batch bucket edge
 """
 from __future__ import annotations
 
@@ -330,9 +331,10 @@ def autotune(dtype, *, method="chol", precision="plain", ns_steps=None, orders=(
              batch=65536, cache=None, device=None) -> int:
     """Time the candidate engines for each order in ``orders`` (inclusive range
     within 1..16) on the current device and stream and record the fastest for
-    later calls with the same dtype, method and precision.  ``cache``: a text
-    file whose entries for this device are loaded instead of measured (new
-    ones are appended).  Returns the number of orders measured."""
+    later calls with the same dtype, method and precision; ``orders = (n, n)``
+    with n > 64 times the large-order configurations at order n instead.
+    ``cache``: a text file whose entries for this device are loaded instead of
+    measured (new ones are appended).  Returns the number of orders measured."""
     if ns_steps is None:
         ns_steps = 1 if precision == "mixed" else 0
     opts = L.make_opts(method, precision, ns_steps, True)
@@ -353,8 +355,39 @@ def tuned_engine(dtype, n, *, method="chol", precision="plain") -> int:
     return int(rc)
 
 
+def autotune_varlen(packed: torch.Tensor, sizes: torch.Tensor, offsets: torch.Tensor, *,
+                    n_max: int | None = None, method="chol", precision="plain", ns_steps=None,
+                    workspace: torch.Tensor | None = None) -> int:
+    """Time the uneven-batch path on this batch for each edge of its last size
+    bucket (33, 25, 17) and record the fastest for later ``inverse_varlen``
+    calls with the same dtype, method and precision.  Returns the edge."""
+    _check_device(packed, sizes, offsets)
+    if ns_steps is None:
+        ns_steps = 1 if precision == "mixed" else 0
+    sizes = sizes.to(torch.int32).contiguous()
+    offsets = offsets.to(torch.int64).contiguous()
+    B = sizes.shape[0]
+    if n_max is None:
+        n_max = int(sizes.max()) if B else 1
+    X = torch.empty_like(packed)
+    opts = L.make_opts(method, precision, ns_steps, True)
+    lib = L.lib()
+    dt = _dtype_code(packed)
+    ws = lib.chol_workspace_size(L.CI_FN_BATCHED, dt, B, 0, ctypes.byref(opts))
+    if workspace is None or workspace.numel() < ws:
+        workspace = _workspace(ws, packed.device)
+    rc = lib.chol_autotune_varlen(dt, ctypes.byref(opts), B, _ptr(sizes), _ptr(offsets),
+                                  int(n_max), _ptr(packed), _ptr(X), _ptr(workspace), ws,
+                                  _stream(packed.device))
+    if rc < 0:
+        L.check("chol_autotune_varlen", rc)
+    return int(rc)
+
+
 def tune_set(dtype, n, engine, *, method="chol", precision="plain") -> None:
-    """Record ``engine`` for order n without measuring (0 = built-in choice)."""
+    """Record ``engine`` for order n without measuring (0 = built-in choice);
+    n > 64: a large-order configuration for n's bucket; n = 0: the
+    uneven-batch bucket edge."""
     opts = L.make_opts(method, precision, 0, True)
     L.check("chol_tune_set", L.lib().chol_tune_set(_code_of(dtype), ctypes.byref(opts), int(n),
                                                    int(engine)))
@@ -386,6 +419,10 @@ class CholInverse(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, A, method="chol", precision="plain", ns_steps=None):
+        if A.requires_grad and A.dtype == torch.complex128 and A.shape[-1] > 32:
+            # the adjoint of complex128 orders 33..64 would need three 64 x 64
+            # complex128 matrices (200 KB) in one workgroup's LDS
+            raise RuntimeError("CholInverse: no backward for complex128 orders above 32")
         X = inverse(A, method=method, precision=precision, ns_steps=ns_steps, fill_lower=True)
         ctx.save_for_backward(X)
         return X

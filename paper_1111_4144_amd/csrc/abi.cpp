@@ -105,7 +105,8 @@ int chol_factor(int dtype, int64_t batch, int64_t n, void* a, int64_t lda, int64
     if (n > CI_SMALL_NMAX) {
         size_t need = ci::large_workspace(dtype, n, ci::LG_FACTOR, 0);
         if (work_bytes < need || (need && !work)) return CI_ERR_WORKSPACE;
-        return map_err(ci::large_factor(dtype, n, a, lda, info, work, s));
+        return map_err(ci::large_factor(dtype, n, a, lda, info, work, s,
+                                        ci::tuned_large(dtype, 0, CI_METHOD_CHOL, n)));
     }
     ci::BatchArgs p{a, a, batch, lda, batch > 1 ? stride : lda * n, lda,
                     batch > 1 ? stride : lda * n, 0, 0, info, nullptr};
@@ -285,8 +286,9 @@ int chol_inverse(int dtype, int64_t n, const void* a, int64_t lda, void* x, int6
         size_t need = ci::large_workspace(dtype, n, ci::LG_INVERSE, o.precision == CI_MIXED);
         if (work_bytes < need || (need && !work)) return CI_ERR_WORKSPACE;
         if (o.method != CI_METHOD_CHOL) return CI_ERR_UNSUPPORTED;
-        return map_err(ci::large_inverse(dtype, n, a, lda, x, ldx, o.precision == CI_MIXED,
-                                         o.ns_steps, o.fill_lower, info, work, s));
+        return map_err(ci::large_inverse(
+            dtype, n, a, lda, x, ldx, o.precision == CI_MIXED, o.ns_steps, o.fill_lower, info, work,
+            s, ci::tuned_large(dtype, o.precision == CI_MIXED, o.method, n)));
     }
     if (a == x && (o.precision == CI_MIXED || lda != ldx)) return -5;
     ci::BatchArgs p{a, x, 1, lda, lda * n, ldx, ldx * n, o.ns_steps, o.fill_lower, info, nullptr};
@@ -317,9 +319,10 @@ int chol_inverse_batched(int dtype, int64_t batch, int64_t n_uniform, const int3
     if (varlen) {
         size_t need = ci::varlen_workspace(batch);
         if (work_bytes < need || !work) return CI_ERR_WORKSPACE;
-        return map_err(ci::launch_varlen(dtype, batch, n_dev, offsets_dev, (int)n_max, a, x,
-                                         o.method, o.precision == CI_MIXED, o.ns_steps,
-                                         o.fill_lower, info, work, s));
+        return map_err(ci::launch_varlen(
+            dtype, batch, n_dev, offsets_dev, (int)n_max, a, x, o.method, o.precision == CI_MIXED,
+            o.ns_steps, o.fill_lower, info, work, s,
+            ci::tuned_varlen(dtype, o.precision == CI_MIXED, o.method)));
     }
     ci::BatchArgs p{a, x, batch, n_uniform, stride_a, n_uniform, stride_x, o.ns_steps,
                     o.fill_lower, info, nullptr};
@@ -420,6 +423,11 @@ int chol_autotune(int dtype, const ci_opts* opts, int n_lo, int n_hi, int64_t ba
     if (!valid_dtype(dtype)) return -1;
     ci_opts o = opts ? *opts : default_opts();
     if (check_opts(o, dtype)) return -2;
+    if (n_lo > CI_SMALL_NMAX && n_hi == n_lo) {
+        if (o.method != CI_METHOD_CHOL) return -2;
+        return ci::autotune_large(dtype, o.precision == CI_MIXED, o.method, o.ns_steps, n_lo,
+                                  cache_path, (hipStream_t)stream);
+    }
     if (n_lo < 1 || n_lo > 16) return -3;
     if (n_hi < n_lo || n_hi > 16) return -4;
     if (batch < 1) return -5;
@@ -432,8 +440,11 @@ int chol_tuned_engine(int dtype, const ci_opts* opts, int n)
     if (!valid_dtype(dtype)) return -1;
     ci_opts o = opts ? *opts : default_opts();
     if (check_opts(o, dtype)) return -2;
-    if (n < 0 || n > CI_SMALL_NMAX) return -3;
-    return ci::tuned_engine(dtype, o.precision == CI_MIXED, o.method, n);
+    if (n < 0) return -3;
+    const int mixed = o.precision == CI_MIXED;
+    if (n == 0) return ci::tuned_varlen(dtype, mixed, o.method);
+    if (n > CI_SMALL_NMAX) return ci::tuned_large(dtype, mixed, o.method, n);
+    return ci::tuned_engine(dtype, mixed, o.method, n);
 }
 
 int chol_tune_set(int dtype, const ci_opts* opts, int n, int engine)
@@ -441,10 +452,39 @@ int chol_tune_set(int dtype, const ci_opts* opts, int n, int engine)
     if (!valid_dtype(dtype)) return -1;
     ci_opts o = opts ? *opts : default_opts();
     if (check_opts(o, dtype)) return -2;
+    const int mixed = o.precision == CI_MIXED;
+    if (n == 0) {
+        if (engine != 0 && engine != 17 && engine != 25 && engine != 33) return -4;
+        ci::tune_set_varlen(dtype, mixed, o.method, engine);
+        return 0;
+    }
+    if (n > CI_SMALL_NMAX) {
+        if (engine < 0 || engine >= ci::large_config_count()) return -4;
+        ci::tune_set_large(dtype, mixed, o.method, n, engine);
+        return 0;
+    }
     if (n < 1 || n > 16) return -3;
-    if (!ci::engine_valid(dtype, o.precision == CI_MIXED, n, engine)) return -4;
-    ci::tune_set(dtype, o.precision == CI_MIXED, o.method, n, engine);
+    if (!ci::engine_valid(dtype, mixed, n, engine)) return -4;
+    ci::tune_set(dtype, mixed, o.method, n, engine);
     return 0;
+}
+
+int chol_autotune_varlen(int dtype, const ci_opts* opts, int64_t batch, const int32_t* n_dev,
+                         const int64_t* offsets_dev, int64_t n_max, const void* a, void* x,
+                         void* work, size_t work_bytes, void* stream)
+{
+    if (!valid_dtype(dtype) || (dtype != CI_F32 && dtype != CI_F64)) return -1;
+    ci_opts o = opts ? *opts : default_opts();
+    if (check_opts(o, dtype)) return -2;
+    if (batch < 1) return -3;
+    if (!n_dev) return -4;
+    if (!offsets_dev) return -5;
+    if (n_max < 1 || n_max > CI_SMALL_NMAX) return -6;
+    if (!a) return -7;
+    if (!x || x == a) return -8;
+    if (work_bytes < ci::varlen_workspace(batch) || !work) return CI_ERR_WORKSPACE;
+    return ci::autotune_varlen(dtype, o.precision == CI_MIXED, o.method, o.ns_steps, batch, n_dev,
+                               offsets_dev, (int)n_max, a, x, work, (hipStream_t)stream);
 }
 
 void chol_autotune_clear(void) { ci::autotune_clear(); }

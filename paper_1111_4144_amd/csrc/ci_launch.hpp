@@ -68,6 +68,19 @@ void autotune_clear();
 // and recording a choice made by the caller.
 bool engine_valid(int dtype, int mixed, int n, int engine);
 void tune_set(int dtype, int mixed, int method, int n, int engine);
+// Large orders: the recorded configuration of n's power-of-two bucket (0 =
+// built-in); measuring the configurations on a test matrix of order n.
+int tuned_large(int dtype, int mixed, int method, int64_t n);
+void tune_set_large(int dtype, int mixed, int method, int64_t n, int cfg);
+int autotune_large(int dtype, int mixed, int method, int ns_steps, int64_t n,
+                   const char* cache_path, hipStream_t s);
+// Uneven batches: the recorded first order of the last bucket (0 = built-in,
+// 33); measuring the candidates on the caller's batch (x is overwritten).
+int tuned_varlen(int dtype, int mixed, int method);
+void tune_set_varlen(int dtype, int mixed, int method, int big_from);
+int autotune_varlen(int dtype, int mixed, int method, int ns_steps, int64_t batch,
+                    const int32_t* n_dev, const int64_t* off_dev, int n_max, const void* a, void* x,
+                    void* work, hipStream_t s);
 
 int tpm_nmax(int dtype, int mixed);
 

@@ -227,8 +227,8 @@ k_lg_diag_factor(T* __restrict__ W, int64_t ldw, int r0, int nl, const double* _
     // column j, y_jj = 1/r_jj and y_ij = -(1/r_ii) sum_{k=i+1..j} r_ik y_kj for
     // i down to the sub-block's first row (entries not computed yet are zero,
     // and R is zero below its diagonal, so the packets may start below i+1;
-    // the lanes of column j are adjacent in one wave, so lane 0's write of
-    // y_ij precedes every lane's later reads).  Then block rows bottom-up:
+    // the lanes of column j are adjacent in one wave, and a wavefront-scope
+    // fence orders lane 0's write of y_ij before every lane's later reads).  Then block rows bottom-up:
     // Y_{I,>I} = -Y_II (R_{I,>I} Y_{>I,>I}), each a parallel stage.
     if (h == 0) Ym[j * LD + j] = sv[j];
     {
@@ -243,6 +243,11 @@ k_lg_diag_factor(T* __restrict__ W, int64_t ldw, int r0, int nl, const double* _
             }
             dot = lg_colsum(dot);
             if (h == 0) Ym[j * LD + i] = -sv[i] * dot;
+            // the next row's sums read y_ij: lane 0's write precedes them (the
+            // lanes of a column are in one wave)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
     }
     __syncthreads();
@@ -281,6 +286,263 @@ k_lg_diag_factor(T* __restrict__ W, int64_t ldw, int r0, int nl, const double* _
     }
     for (int i = h; i < NB; i += LG_TPC) rinv[(int64_t)i * NB + j] = (i <= j) ? Ym[j * LD + i] : T(0);
     if (threadIdx.x == 0 && fail && info && info[0] == 0) info[0] = r0 + fail;
+}
+
+// ---- diagonal block, sub-blocked on the matrix cores -------------------------------
+// Cholesky of the diagonal block and R_II^{-1}, four waves.  Sub-blocks of
+// LF_SB columns: wave 0 factors the diagonal sub-block in registers (one lane
+// per column; row i of R reaches every lane by readlane from its owners; FP64
+// pivot accumulators in mixed precision) and inverts it the same way; then all
+// waves apply it with MFMA 16x16x4 tiles: the sub-block's panel row
+// R_{b,>b} = R_bb^{-T} A_{b,>b} and the upper part of A_{>b,>b} -= R_{b,>b}^T R_{b,>b}.
+// Last, the off-diagonal blocks of R^{-1}, block rows bottom-up:
+// Y_{a,>a} = -Y_aa (R_{a,>a} Y_{>a,>a}), as MFMA tiles.  One workgroup barrier
+// separates the phases (five per sub-block and four per inverse block row)
+// instead of one per row.
+constexpr int LF_SB = 16;
+constexpr int LF_THREADS = 256;
+template <class T> constexpr int LF_LD = LG_NB<T> + 16 / (int)sizeof(T);   // padded row
+template <class T> constexpr size_t lf_smem()
+{
+    return (size_t)2 * LG_NB<T> * LF_LD<T> * sizeof(T) + LG_NB<T> * sizeof(double);
+}
+
+template <class T>
+__device__ __forceinline__ T lf_bcast(T v, int src)
+{
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
+    } else {
+        const uint64_t u = __builtin_bit_cast(uint64_t, v);
+        const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)u, src);
+        const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), src);
+        return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+    }
+}
+
+// One 16 x 16 output tile: d += sum_k A(r, k) B(k, c) for k in [0, K), K a
+// multiple of 4; lane (g, cc) supplies A(cc, k + g) and B(k + g, cc).
+template <class T, class FA, class FB>
+__device__ __forceinline__ void lf_tile(typename mfma_acc<T>::type& d, int K, int g, int cc, FA fa,
+                                        FB fb)
+{
+    for (int k = 0; k < K; k += 4) d = mfma16(fa(cc, k + g), fb(k + g, cc), d);
+}
+
+template <class T, int MIXED>
+__global__ void __launch_bounds__(LF_THREADS)
+k_lg_leaf(T* __restrict__ W, int64_t ldw, int r0, int nl, const double* __restrict__ dacc,
+          T* __restrict__ rinv, int32_t* __restrict__ info)
+{
+    constexpr int NB = LG_NB<T>, LD = LF_LD<T>, SB = LF_SB, NSB = NB / SB;
+    using Acc = typename mfma_acc<T>::type;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* Rm = reinterpret_cast<T*>(smem_raw);              // R, row major, upper
+    T* Ym = Rm + NB * LD;                                // R^{-1}, row major, upper
+    double* dl = reinterpret_cast<double*>(Ym + NB * LD); // FP64 pivot accumulators
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    const int g = lane / 16, cc = lane % 16;
+    T* Wb = W + (int64_t)r0 * ldw + r0;
+    // the block's upper triangle (identity beyond nl); Y starts at zero.  All
+    // of a lane's loads are issued before its first LDS store, so the global
+    // latency is paid once, not once per element.
+    {
+        constexpr int PER = NB * NB / LF_THREADS;
+        T v[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = tid + LF_THREADS * u, k = e / NB, j = e % NB;
+            v[u] = (k == j) ? T(1) : T(0);
+            if (j < nl && k < nl && k <= j) v[u] = Wb[(int64_t)k * ldw + j];
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = tid + LF_THREADS * u, k = e / NB, j = e % NB;
+            Rm[k * LD + j] = (k <= j) ? v[u] : T(0);
+            Ym[k * LD + j] = T(0);
+        }
+    }
+    if (MIXED)
+        for (int j = tid; j < NB; j += LF_THREADS) dl[j] = (j < nl) ? dacc[r0 + j] : 1.0;
+    __syncthreads();
+    int fail = 0;
+
+    for (int b = 0; b < NSB; ++b) {
+        const int b0 = b * SB, b1 = b0 + SB, nr = NB - b1;
+        // ---- wave 0: factor and invert the diagonal sub-block in registers
+        if (wave == 0) {
+            const int j = lane;                       // column b0 + j (lanes >= SB idle)
+            T c[SB];
+#pragma unroll
+            for (int k = 0; k < SB; ++k)
+                c[k] = (j < SB && k <= j) ? Rm[(b0 + k) * LD + b0 + j] : T(0);
+            double dj = (MIXED && j < SB) ? dl[b0 + j] : 0.0;
+            T sv[SB];                                 // 1/r_kk, uniform
+#pragma unroll
+            for (int i = 0; i < SB; ++i) {
+                const double piv = MIXED ? dj : (double)c[i];
+                T rii, si;
+                if constexpr (sizeof(T) == 4) {
+                    double r, y;
+                    sqrt_rsqrt_est(piv, r, y);
+                    rii = (T)r;
+                    si = (T)y;
+                } else {
+                    const double r = sqrt(piv);
+                    rii = (T)r;
+                    si = (T)(1.0 / r);
+                }
+                const int okl = (piv > 0.0 && piv < __builtin_inf()) ? 1 : 0;
+                const int ok = __builtin_amdgcn_readlane(okl, i);
+                if (!ok && !fail && b0 + i < nl) fail = b0 + i + 1;
+                const T s_i = lf_bcast(si, i), r_ii = lf_bcast(rii, i);
+                sv[i] = s_i;
+                c[i] = (j > i) ? c[i] * s_i : ((j == i) ? r_ii : c[i]);
+                if (MIXED && j > i) dj = fma(-(double)c[i], (double)c[i], dj);
+#pragma unroll
+                for (int k = i + 1; k < SB; ++k) c[k] -= lf_bcast(c[i], k) * c[i];
+            }
+            // Y_bb: column j by back-substitution, rows j-1 .. 0
+            T y[SB];
+#pragma unroll
+            for (int k = SB - 1; k >= 0; --k) {
+                T acc = T(0);
+#pragma unroll
+                for (int m = k + 1; m < SB; ++m) acc += lf_bcast(c[k], m) * y[m];
+                y[k] = (j > k) ? -sv[k] * acc : ((j == k) ? sv[k] : T(0));
+            }
+            if (j < SB) {
+#pragma unroll
+                for (int k = 0; k < SB; ++k) {
+                    if (k <= j) {
+                        Rm[(b0 + k) * LD + b0 + j] = c[k];
+                        Ym[(b0 + k) * LD + b0 + j] = y[k];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (nr == 0) break;
+        // ---- panel row R_{b,>b} = Y_bb^T A_{b,>b} (tiles held in registers
+        // until every wave has read A_{b,>b})
+        constexpr int PT_MAX = (SB / 16) * ((NB - SB) / 16);
+        constexpr int PT_PER = (PT_MAX + 3) / 4;
+        const int ptn = nr / 16, pt = (SB / 16) * ptn;
+        Acc pacc[PT_PER];
+#pragma unroll
+        for (int u = 0; u < PT_PER; ++u) {
+            pacc[u] = Acc{0, 0, 0, 0};
+            const int t = wave + 4 * u;
+            if (t < pt) {
+                const int tr = t / ptn, tc = t % ptn;
+                lf_tile<T>(pacc[u], SB, g, cc,
+                           [&](int r, int k) { return Ym[(b0 + k) * LD + b0 + 16 * tr + r]; },
+                           [&](int k, int cl) { return Rm[(b0 + k) * LD + b1 + 16 * tc + cl]; });
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < PT_PER; ++u) {
+            const int t = wave + 4 * u;
+            if (t < pt) {
+                const int tr = t / ptn, tc = t % ptn;
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    Rm[(b0 + 16 * tr + mfma_acc<T>::row(g, v)) * LD + b1 + 16 * tc + cc] = pacc[u][v];
+            }
+        }
+        __syncthreads();
+        // ---- FP64 pivots of the remaining columns, and the upper part of
+        // A_{>b,>b} -= R_{b,>b}^T R_{b,>b}
+        if (MIXED) {
+            for (int jj = tid; jj < nr; jj += LF_THREADS) {
+                double q = dl[b1 + jj];
+#pragma unroll 8
+                for (int k = 0; k < SB; ++k) {
+                    const double v = (double)Rm[(b0 + k) * LD + b1 + jj];
+                    q = fma(-v, v, q);
+                }
+                dl[b1 + jj] = q;
+            }
+        }
+        const int st = ptn * (ptn + 1) / 2;
+        for (int t = wave; t < st; t += 4) {
+            int tr = 0, rem = t;
+            while (rem >= ptn - tr) { rem -= ptn - tr; ++tr; }
+            const int tc = tr + rem;
+            Acc d = Acc{0, 0, 0, 0};
+            lf_tile<T>(d, SB, g, cc,
+                       [&](int r, int k) { return Rm[(b0 + k) * LD + b1 + 16 * tr + r]; },
+                       [&](int k, int cl) { return Rm[(b0 + k) * LD + b1 + 16 * tc + cl]; });
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = b1 + 16 * tr + mfma_acc<T>::row(g, v), jc = b1 + 16 * tc + cc;
+                if (jc >= i) Rm[i * LD + jc] -= d[v];
+            }
+        }
+        __syncthreads();
+    }
+    // ---- off-diagonal blocks of Y = R^{-1}, block rows bottom-up
+    for (int a = NSB - 2; a >= 0; --a) {
+        const int a0 = a * SB, b1 = a0 + SB, nr = NB - b1, ptn = nr / 16, pt = (SB / 16) * ptn;
+        constexpr int PT_PER = ((SB / 16) * ((NB - SB) / 16) + 3) / 4;
+        Acc tacc[PT_PER];
+        // T = R_{a,>a} Y_{>a,>a} (Y upper triangular: zero below its diagonal)
+#pragma unroll
+        for (int u = 0; u < PT_PER; ++u) {
+            tacc[u] = Acc{0, 0, 0, 0};
+            const int t = wave + 4 * u;
+            if (t < pt) {
+                const int tr = t / ptn, tc = t % ptn;
+                lf_tile<T>(tacc[u], 16 * (tc + 1), g, cc,
+                           [&](int r, int k) { return Rm[(a0 + 16 * tr + r) * LD + b1 + k]; },
+                           [&](int k, int cl) { return Ym[(b1 + k) * LD + b1 + 16 * tc + cl]; });
+            }
+        }
+        // T goes into Y_{a,>a} (still zero, read by nobody in this product)
+#pragma unroll
+        for (int u = 0; u < PT_PER; ++u) {
+            const int t = wave + 4 * u;
+            if (t < pt) {
+                const int tr = t / ptn, tc = t % ptn;
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    Ym[(a0 + 16 * tr + mfma_acc<T>::row(g, v)) * LD + b1 + 16 * tc + cc] = tacc[u][v];
+            }
+        }
+        __syncthreads();
+        // Y_{a,>a} = -Y_aa T (Y_aa upper triangular)
+#pragma unroll
+        for (int u = 0; u < PT_PER; ++u) {
+            tacc[u] = Acc{0, 0, 0, 0};
+            const int t = wave + 4 * u;
+            if (t < pt) {
+                const int tr = t / ptn, tc = t % ptn;
+                lf_tile<T>(tacc[u], SB, g, cc,
+                           [&](int r, int k) { return Ym[(a0 + 16 * tr + r) * LD + a0 + k]; },
+                           [&](int k, int cl) { return Ym[(a0 + k) * LD + b1 + 16 * tc + cl]; });
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < PT_PER; ++u) {
+            const int t = wave + 4 * u;
+            if (t < pt) {
+                const int tr = t / ptn, tc = t % ptn;
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    Ym[(a0 + 16 * tr + mfma_acc<T>::row(g, v)) * LD + b1 + 16 * tc + cc] = -tacc[u][v];
+            }
+        }
+        __syncthreads();
+    }
+    // ---- R back to W (upper triangle of the block), R^{-1} to rinv
+    for (int e = tid; e < NB * NB; e += LF_THREADS) {
+        const int k = e / NB, j = e % NB;
+        if (k <= j && j < nl) Wb[(int64_t)k * ldw + j] = Rm[k * LD + j];
+        rinv[(int64_t)k * NB + j] = (k <= j) ? Ym[k * LD + j] : T(0);
+    }
+    if (tid == 0 && fail && info && info[0] == 0) info[0] = r0 + fail;
 }
 
 // ---- FP64 pivot accumulators: d_j -= sum_{k in panel} r_kj^2, j >= c0 ----------
@@ -496,15 +758,18 @@ static hipError_t gemm(int M, int N, int K, double alpha, const TA* A, int64_t l
 }
 
 // C (m x n) = alpha * A B with K split over partial products so that about
-// 512 workgroups run (two per CU), each split at least 64 deep, the partials
+// g_splitk_target workgroups run, each split at least kmin deep, the partials
 // within the workspace's capacity `cap` (elements)
+// The target workgroup count is the tuned configuration's (512 by default).
+static thread_local int g_splitk_target = 512;
+
 template <class T>
 static hipError_t gemm_splitk(int M, int N, int K, double alpha, const T* A, int64_t lda, int ta,
                               const T* B, int64_t ldb, int tb, T* C, int64_t ldc, T* part,
                               int64_t cap, hipStream_t s, int tri = 0, int kmin = 64)
 {
     const int tiles = ((M + GT_M - 1) / GT_M) * ((N + GT_N - 1) / GT_N);
-    int splits = (512 + tiles - 1) / tiles;
+    int splits = (g_splitk_target + tiles - 1) / tiles;
     splits = std::min<int64_t>(splits, std::max(1, K / kmin));
     splits = (int)std::min<int64_t>(splits, cap / ((int64_t)M * N));
     if (splits <= 1)
@@ -525,16 +790,34 @@ static hipError_t gemm_splitk(int M, int N, int K, double alpha, const T* A, int
     return hipGetLastError();
 }
 
+// Configurations of the large-order path the tuner chooses between:
+//   diag    0 = diagonal blocks sub-blocked on MFMA (k_lg_leaf), 1 = the
+//           Crout recurrence with one barrier per row (k_lg_diag_factor)
+//   inv     0 = blocked triangular inverse + X = M M^T, 1 = the Section IV
+//           recurrence in block form
+//   splitk  target workgroups of the split-K products
+struct LgCfg { int diag, inv, splitk; };
+static const LgCfg LG_CFGS[] = {{0, 0, 512}, {0, 0, 256}, {0, 0, 1024}, {1, 0, 512}, {0, 1, 512}};
+constexpr int LG_NCFG = sizeof(LG_CFGS) / sizeof(LG_CFGS[0]);
+static thread_local LgCfg g_cfg = LG_CFGS[0];
+
+int large_config_count() { return LG_NCFG; }
+static int lg_diag_engine() { return g_cfg.diag; }
+
 template <class T, int MIXED>
 static hipError_t lg_factor(T* W, int64_t n, double* dacc, T* rinv, T* part, int64_t part_cap,
                             int32_t* info, hipStream_t s)
 {
     constexpr int NB = LG_NB<T>;
-    const size_t smem = lg_diag_smem<T>();
+    const size_t smem = lg_diag_smem<T>(), smem_leaf = lf_smem<T>();
+    const bool leaf = lg_diag_engine() == 0;
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void*)k_lg_diag_factor<T, MIXED>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+        if (e != hipSuccess) return e;
+        e = hipFuncSetAttribute((const void*)k_lg_leaf<T, MIXED>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem_leaf);
         if (e != hipSuccess) return e;
         attr = true;
     }
@@ -542,8 +825,12 @@ static hipError_t lg_factor(T* W, int64_t n, double* dacc, T* rinv, T* part, int
         const int nl = (int)std::min<int64_t>(NB, n - r0);
         const int64_t c0 = r0 + nl, mr = n - c0;
         T* rv = rinv + (r0 / NB) * NB * NB;
-        hipLaunchKernelGGL((k_lg_diag_factor<T, MIXED>), dim3(1), dim3(NB * LG_TPC), smem, s, W, n, (int)r0,
-                           nl, dacc, rv, info);
+        if (leaf)
+            hipLaunchKernelGGL((k_lg_leaf<T, MIXED>), dim3(1), dim3(LF_THREADS), smem_leaf, s, W, n,
+                               (int)r0, nl, dacc, rv, info);
+        else
+            hipLaunchKernelGGL((k_lg_diag_factor<T, MIXED>), dim3(1), dim3(NB * LG_TPC), smem, s, W, n,
+                               (int)r0, nl, dacc, rv, info);
         if (mr <= 0) break;
         // R_I,>I = R_II^{-T} A_I,>I over one tile row: K split (32 deep) so that
         // the GPU fills; the partials are reduced into place after every split
@@ -657,16 +944,8 @@ static hipError_t lg_lauum(const T* W, int64_t n, T* X, int64_t ldx, hipStream_t
 }
 
 // Inverse from the factor: TRTRI + M M^T (default), or the Section IV
-// recurrence in block form (environment CHOLINV_LARGE_INVERSE=blocked_iv).
-static int lg_use_blocked_iv()
-{
-    static int v = -1;
-    if (v < 0) {
-        const char* e = std::getenv("CHOLINV_LARGE_INVERSE");
-        v = (e && std::strcmp(e, "blocked_iv") == 0) ? 1 : 0;
-    }
-    return v;
-}
+// recurrence in block form (configuration inv = 1).
+static int lg_use_blocked_iv() { return g_cfg.inv; }
 
 template <class T, int MIXED>
 static hipError_t lg_inverse(int64_t n, const T* a, int64_t lda, T* x, int64_t ldx, int ns_steps,
@@ -735,9 +1014,18 @@ size_t large_workspace(int dtype, int64_t n, int which, int mixed)
     return 0;
 }
 
-hipError_t large_factor(int dtype, int64_t n, void* a, int64_t lda, int32_t* info, void* work,
-                        hipStream_t s)
+// Selects configuration `cfg` (0..large_config_count()-1) for the calls that
+// follow on this host thread.
+static void lg_select(int cfg)
 {
+    g_cfg = LG_CFGS[(cfg >= 0 && cfg < LG_NCFG) ? cfg : 0];
+    g_splitk_target = g_cfg.splitk;
+}
+
+hipError_t large_factor(int dtype, int64_t n, void* a, int64_t lda, int32_t* info, void* work,
+                        hipStream_t s, int cfg)
+{
+    lg_select(cfg);
     // in place on a (leading dimension lda must equal n for the blocked path)
     if (lda != n) return hipErrorNotSupported;
     if (info) {
@@ -763,9 +1051,11 @@ hipError_t large_factor(int dtype, int64_t n, void* a, int64_t lda, int32_t* inf
 }
 
 hipError_t large_inverse(int dtype, int64_t n, const void* a, int64_t lda, void* x, int64_t ldx,
-                         int mixed, int ns_steps, int fill, int32_t* info, void* work, hipStream_t s)
+                         int mixed, int ns_steps, int fill, int32_t* info, void* work, hipStream_t s,
+                         int cfg)
 {
     (void)fill;   // the blocked path always writes both halves (the GEMMs read them)
+    lg_select(cfg);
     if (dtype == DT_F32) {
         if (mixed)
             return lg_inverse<float, 1>(n, static_cast<const float*>(a), lda, static_cast<float*>(x),

@@ -16,6 +16,7 @@
 #include <mutex>
 #include <string>
 
+#include "ci_large.hpp"
 #include "ci_launch.hpp"
 #include "ci_types.hpp"
 #include "cholinv.h"
@@ -27,6 +28,17 @@ namespace {
 std::mutex g_mu;
 // [dtype][mixed][method][n] -> engine (0 = built-in default)
 int g_table[4][2][2][65];
+// large orders: [dtype][mixed][method][floor(log2 n)] -> configuration index
+int g_large[4][2][2][32];
+// uneven batches: [dtype][mixed][method] -> first order of the last bucket (0 = 33)
+int g_varlen[4][2][2];
+
+int log2_bucket(int64_t n)
+{
+    int b = 0;
+    while (b < 31 && ((int64_t)2 << b) <= n) ++b;
+    return b;
+}
 
 std::string device_key()
 {
@@ -88,6 +100,9 @@ int candidates(int dtype, int mixed, int n, int* out)
     return k;
 }
 
+// Cache lines: "cholinv-tune v1 <device> dtype mixed method n choice us"; n in
+// 1..16 records an engine, n > 64 a large-order configuration (for the
+// order's power-of-two bucket), n = 0 the uneven-batch bucket edge.
 bool load_cache(const char* path, const std::string& dev, int dtype, int mixed, int method,
                 int n_lo, int n_hi, bool* have)
 {
@@ -103,6 +118,12 @@ bool load_cache(const char* path, const std::string& dev, int dtype, int mixed, 
             continue;
         if (dev != dname || d != dtype || p != mixed || m != method || n < n_lo || n > n_hi)
             continue;
+        if (n > 64) {
+            if (e < 0 || e >= large_config_count()) continue;
+            g_large[dtype][mixed][method][log2_bucket(n)] = e;
+            have[0] = true;
+            continue;
+        }
         if (e < ENG_DEFAULT || e > ENG_QUAD16) continue;
         g_table[dtype][mixed][method][n] = e;
         have[n] = true;
@@ -225,6 +246,147 @@ void autotune_clear()
 {
     std::lock_guard<std::mutex> lk(g_mu);
     std::memset(g_table, 0, sizeof g_table);
+    std::memset(g_large, 0, sizeof g_large);
+    std::memset(g_varlen, 0, sizeof g_varlen);
+}
+
+// ---- large orders ---------------------------------------------------------------
+int tuned_large(int dtype, int mixed, int method, int64_t n)
+{
+    if (dtype < 0 || dtype > 3) return 0;
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_large[dtype][mixed ? 1 : 0][method ? 1 : 0][log2_bucket(n)];
+}
+
+void tune_set_large(int dtype, int mixed, int method, int64_t n, int cfg)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_large[dtype][mixed ? 1 : 0][method ? 1 : 0][log2_bucket(n)] = cfg;
+}
+
+namespace {
+// symmetric positive definite test matrix a_ij = 1/(1 + |i - j|) + n [i == j]
+template <class T>
+__global__ void k_tune_spd(T* a, int64_t n)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * n) return;
+    const int64_t i = e / n, j = e % n, d = i > j ? i - j : j - i;
+    a[e] = T(1) / T(1 + d) + (i == j ? T(n) : T(0));
+}
+}  // namespace
+
+int autotune_large(int dtype, int mixed, int method, int ns_steps, int64_t n, const char* cache_path,
+                   hipStream_t s)
+{
+    if (dtype != DT_F32 && dtype != DT_F64) return -1000 - (int)hipErrorNotSupported;
+    const std::string dev = device_key();
+    bool have[65] = {false};
+    if (cache_path) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        load_cache(cache_path, dev, dtype, mixed, method, (int)n, (int)n, have);
+        if (have[0]) return 0;
+    }
+    const size_t es = dtype == DT_F32 ? 4 : 8, bytes = (size_t)n * n * es;
+    const size_t wbytes = large_workspace(dtype, n, LG_INVERSE, mixed);
+    void *a = nullptr, *x = nullptr, *w = nullptr;
+    if (hipMalloc(&a, bytes) != hipSuccess) return -1000 - (int)hipErrorOutOfMemory;
+    if (hipMalloc(&x, bytes) != hipSuccess) { (void)hipFree(a); return -1000 - (int)hipErrorOutOfMemory; }
+    if (hipMalloc(&w, wbytes) != hipSuccess) {
+        (void)hipFree(a); (void)hipFree(x);
+        return -1000 - (int)hipErrorOutOfMemory;
+    }
+    const unsigned blocks = (unsigned)((n * n + 255) / 256);
+    if (dtype == DT_F32) hipLaunchKernelGGL(k_tune_spd<float>, dim3(blocks), dim3(256), 0, s, (float*)a, n);
+    else hipLaunchKernelGGL(k_tune_spd<double>, dim3(blocks), dim3(256), 0, s, (double*)a, n);
+    hipError_t err = hipGetLastError();
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    int best = 0;
+    float best_ms = 0.f;
+    for (int c = 0; c < large_config_count() && err == hipSuccess; ++c) {
+        err = large_inverse(dtype, n, a, n, x, n, mixed, ns_steps, 1, nullptr, w, s, c);  // warm-up
+        if (err != hipSuccess) break;
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < 2 && err == hipSuccess; ++r)
+            err = large_inverse(dtype, n, a, n, x, n, mixed, ns_steps, 1, nullptr, w, s, c);
+        (void)hipEventRecord(e1, s);
+        if (err != hipSuccess) break;
+        err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (c == 0 || ms < best_ms * 0.99f) {
+            best = c;
+            best_ms = ms;
+        }
+    }
+    if (err == hipSuccess) {
+        tune_set_large(dtype, mixed, method, n, best);
+        FILE* out = cache_path ? std::fopen(cache_path, "a") : nullptr;
+        if (out) {
+            std::fprintf(out, "cholinv-tune v1 %s %d %d %d %lld %d %.3f\n", dev.c_str(), dtype, mixed,
+                         method, (long long)n, best, 1e3 * best_ms / 2);
+            std::fclose(out);
+        }
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(a);
+    (void)hipFree(x);
+    (void)hipFree(w);
+    return err == hipSuccess ? 1 : -1000 - (int)err;
+}
+
+// ---- uneven batches ---------------------------------------------------------------
+int tuned_varlen(int dtype, int mixed, int method)
+{
+    if (dtype < 0 || dtype > 3) return 0;
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_varlen[dtype][mixed ? 1 : 0][method ? 1 : 0];
+}
+
+void tune_set_varlen(int dtype, int mixed, int method, int big_from)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_varlen[dtype][mixed ? 1 : 0][method ? 1 : 0] = big_from;
+}
+
+int autotune_varlen(int dtype, int mixed, int method, int ns_steps, int64_t batch,
+                    const int32_t* n_dev, const int64_t* off_dev, int n_max, const void* a, void* x,
+                    void* work, hipStream_t s)
+{
+    static const int cand[] = {33, 25, 17};
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    hipError_t err = hipSuccess;
+    int best = 33;
+    float best_ms = 0.f;
+    for (int c = 0; c < 3 && err == hipSuccess; ++c) {
+        err = launch_varlen(dtype, batch, n_dev, off_dev, n_max, a, x, method, mixed, ns_steps, 1,
+                            nullptr, work, s, cand[c]);                              // warm-up
+        if (err != hipSuccess) break;
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < 3 && err == hipSuccess; ++r)
+            err = launch_varlen(dtype, batch, n_dev, off_dev, n_max, a, x, method, mixed, ns_steps,
+                                1, nullptr, work, s, cand[c]);
+        (void)hipEventRecord(e1, s);
+        if (err != hipSuccess) break;
+        err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (c == 0 || ms < best_ms * 0.99f) {
+            best = cand[c];
+            best_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return -1000 - (int)err;
+    tune_set_varlen(dtype, mixed, method, best);
+    return best;
 }
 
 }  // namespace ci

@@ -51,15 +51,15 @@ size_t varlen_workspace(int64_t batch)
 
 hipError_t launch_varlen(int dtype, int64_t batch, const int32_t* n_dev, const int64_t* off_dev,
                          int n_max, const void* a, void* x, int method, int mixed, int ns_steps,
-                         int fill, int32_t* info, void* work, hipStream_t s)
+                         int fill, int32_t* info, void* work, hipStream_t s, int big_from)
 {
     switch (dtype) {
     case DT_F32:
         return varlen_dispatch<float>(batch, n_dev, off_dev, n_max, a, x, method, mixed, ns_steps,
-                                      fill, info, work, s);
+                                      fill, info, work, s, big_from);
     case DT_F64:
         return varlen_dispatch<double>(batch, n_dev, off_dev, n_max, a, x, method, mixed, ns_steps,
-                                       fill, info, work, s);
+                                       fill, info, work, s, big_from);
     default:
         return hipErrorNotSupported;
     }

@@ -10,10 +10,12 @@
 // 9..16 up to 4 matrices (16-lane groups padded to 16 with the identity,
 // which leaves the n x n block exact); 17..32 up to 2 (LDS-resident, one lane
 // per column) and 33..64 one matrix (LDS-resident, four lanes per column,
-// four waves).  Two persistent kernels, one per block shape, take tiles from
-// their own atomic counters until none are left (every wave reaches that
-// exit): first orders 33..64, then the rest, largest orders first within
-// each.  Results do not depend on which wave takes which tile.
+// four waves).  The edge of the last bucket (33) can move down to 25 or 17
+// (a tuned choice): those orders then take whole four-wave blocks.  Two
+// persistent kernels, one per block shape, take tiles from their own atomic
+// counters until none are left (every wave reaches that exit): first the
+// last bucket, then the rest, largest orders first within each.  Results do
+// not depend on which wave takes which tile.
 #pragma once
 
 #include "group_impl.hpp"
@@ -25,8 +27,9 @@ namespace ci {
 struct VarlenPlan {
     int next;              // tile counter of the orders <= 32 kernel (starts at nbig)
     int ntiles;
-    int next_big;          // tile counter of the orders 33..64 kernel (starts at 0)
-    int nbig;              // tiles of orders 33..64 (one matrix each, first in the order)
+    int next_big;          // tile counter of the last bucket's kernel (starts at 0)
+    int nbig;              // tiles of orders big_from..64 (one matrix each, first in the order)
+    int big_from;          // smallest order of the four-waves-per-matrix kernel (17, 25 or 33)
     int count[65];         // matrices per order
     int item_start[65];    // first position of order n in the sorted list
     int tile_start[65];    // tile range of order n: [tile_start, tile_end)
@@ -67,13 +70,14 @@ k_vl_count(const int32_t* __restrict__ ns, int64_t batch, int nmax, VarlenPlan* 
         if (local[t]) atomicAdd(&plan->count[t], local[t]);
 }
 
-__global__ void k_vl_scan(VarlenPlan* plan)
+__global__ void k_vl_scan(VarlenPlan* plan, int big_from)
 {
     if (threadIdx.x != 0) return;
     int items = 0, tiles = 0;
+    plan->big_from = big_from;
     for (int n = 64; n >= 1; --n) {
         const int c = plan->count[n];
-        const int ts = vl_tile_size(n);
+        const int ts = n >= big_from ? 1 : vl_tile_size(n);
         plan->item_start[n] = items;
         plan->tile_start[n] = tiles;
         tiles += (c + ts - 1) / ts;
@@ -81,7 +85,7 @@ __global__ void k_vl_scan(VarlenPlan* plan)
         items += c;
     }
     plan->ntiles = tiles;
-    plan->nbig = plan->tile_end[33];
+    plan->nbig = plan->tile_end[big_from];
     plan->next = plan->nbig;
     plan->next_big = 0;
 }
@@ -183,7 +187,8 @@ k_varlen(const V* __restrict__ a, V* x, const int64_t* __restrict__ offs,
     }
 }
 
-// Orders 33..64: one matrix per 256-lane block, four lanes per column.
+// Orders big_from..64 (big_from = 33 by default, 17 or 25 when the tuner
+// finds it faster): one matrix per 256-lane block, four lanes per column.
 constexpr int VL_BIG_TPC = 4;
 
 template <class V, int METHOD, int MIXED>
@@ -202,7 +207,7 @@ k_varlen_big(const V* __restrict__ a, V* x, const int64_t* __restrict__ offs,
         __syncthreads();
         if (t >= plan->nbig) break;
         int n = 64;
-        while (n > 33 && t >= plan->tile_end[n]) --n;
+        while (n > plan->big_from && t >= plan->tile_end[n]) --n;
         const int b = sorted[plan->item_start[n] + (t - plan->tile_start[n])];
         const int64_t o = offs[b];
         wpm_matrix<V, 64, OP_INV, METHOD, MIXED, VL_BIG_TPC>(a + o, x + o, n, true, n, n, ns_steps,
@@ -217,14 +222,15 @@ constexpr size_t varlen_plan_bytes() { return (sizeof(VarlenPlan) + 255) / 256 *
 template <class V, int METHOD, int MIXED>
 static hipError_t varlen_run(int64_t batch, const int32_t* n_dev, const int64_t* off_dev, int n_max,
                              const void* a, void* x, int ns_steps, int fill, int32_t* info,
-                             void* work, hipStream_t s)
+                             void* work, hipStream_t s, int big_from)
 {
+    if (big_from != 17 && big_from != 25) big_from = 33;
     VarlenPlan* plan = reinterpret_cast<VarlenPlan*>(work);
     int32_t* sorted = reinterpret_cast<int32_t*>((char*)work + varlen_plan_bytes());
     const unsigned gb = (unsigned)((batch + 255) / 256);
     hipLaunchKernelGGL(k_vl_init, dim3(1), dim3(256), 0, s, plan);
     hipLaunchKernelGGL(k_vl_count, dim3(gb), dim3(256), 0, s, n_dev, batch, n_max, plan, info);
-    hipLaunchKernelGGL(k_vl_scan, dim3(1), dim3(64), 0, s, plan);
+    hipLaunchKernelGGL(k_vl_scan, dim3(1), dim3(64), 0, s, plan, big_from);
     hipLaunchKernelGGL(k_vl_scatter, dim3(gb), dim3(256), 0, s, n_dev, batch, n_max, plan, sorted);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -250,7 +256,7 @@ static hipError_t varlen_run(int64_t batch, const int32_t* n_dev, const int64_t*
             per_cu = 1;
         return (int64_t)device_cus() * per_cu;
     };
-    if (n_max > 32) {
+    if (n_max >= big_from) {
         hipLaunchKernelGGL(kbig, dim3((unsigned)grid_of((const void*)kbig, 64 * VL_BIG_TPC, s64)),
                            dim3(64 * VL_BIG_TPC), s64, s, (const V*)a, (V*)x, off_dev, sorted, plan,
                            ns_steps, fill, info);
@@ -266,20 +272,25 @@ static hipError_t varlen_run(int64_t batch, const int32_t* n_dev, const int64_t*
 template <class V>
 static hipError_t varlen_dispatch(int64_t batch, const int32_t* n_dev, const int64_t* off_dev,
                                   int n_max, const void* a, void* x, int method, int mixed,
-                                  int ns_steps, int fill, int32_t* info, void* work, hipStream_t s)
+                                  int ns_steps, int fill, int32_t* info, void* work, hipStream_t s,
+                                  int big_from)
 {
     constexpr bool f32 = sizeof(typename vt<V>::real) == 4;
     if (mixed) {
         if constexpr (f32) {
             if (method == 0)
-                return varlen_run<V, 0, 1>(batch, n_dev, off_dev, n_max, a, x, ns_steps, fill, info, work, s);
-            return varlen_run<V, 1, 1>(batch, n_dev, off_dev, n_max, a, x, ns_steps, fill, info, work, s);
+                return varlen_run<V, 0, 1>(batch, n_dev, off_dev, n_max, a, x, ns_steps, fill, info,
+                                           work, s, big_from);
+            return varlen_run<V, 1, 1>(batch, n_dev, off_dev, n_max, a, x, ns_steps, fill, info,
+                                       work, s, big_from);
         }
         return hipErrorNotSupported;
     }
     if (method == 0)
-        return varlen_run<V, 0, 0>(batch, n_dev, off_dev, n_max, a, x, 0, fill, info, work, s);
-    return varlen_run<V, 1, 0>(batch, n_dev, off_dev, n_max, a, x, 0, fill, info, work, s);
+        return varlen_run<V, 0, 0>(batch, n_dev, off_dev, n_max, a, x, 0, fill, info, work, s,
+                                   big_from);
+    return varlen_run<V, 1, 0>(batch, n_dev, off_dev, n_max, a, x, 0, fill, info, work, s,
+                               big_from);
 }
 
 }  // namespace ci

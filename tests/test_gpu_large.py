@@ -222,31 +222,26 @@ def test_large_mixed_refinement_improves():
     assert e1 < 0.5 * e0, (e0, e1)
 
 
-def test_blocked_section_iv_variant():
-    """The Section IV recurrence in block form (selected by the environment in
-    a child process) against the oracle, next to the default inverse."""
-    import os
-    import subprocess
-    import sys
-    torch_cuda()
-    code = r'''
-import numpy as np, torch
-import oracle as O
-from paper_1111_4144_amd import api, inputs as I
-from tests.helpers import rel_err
-worst = 0.0
-for n, dt, prec in [(200, np.float64, "plain"), (333, np.float32, "plain"), (333, np.float32, "mixed")]:
-    a = I.large_spd(n, seed=77 + n, top=1e3)
-    ref, _ = O.inv_prop(a.astype(dt).astype(np.float64))
-    x = api.inverse(torch.from_numpy(a.astype(dt)).cuda(), precision=prec).cpu().numpy()
-    tol = 1e-12 if dt == np.float64 else 2e-6
-    err = float(rel_err(x.astype(np.float64), ref))
-    assert err <= tol * 1e3, (n, prec, err)
-print("blocked_iv ok")
-'''
-    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-    env = dict(os.environ, CHOLINV_LARGE_INVERSE="blocked_iv", PYTHONPATH=root)
-    r = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True,
-                       text=True, timeout=240)
-    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
-    assert "blocked_iv ok" in r.stdout
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4])
+def test_large_configurations_vs_oracle(cfg):
+    """Every large-order configuration (pinned with tune_set for the orders'
+    bucket: split-K targets 256 / 1024, the row-by-row diagonal kernel, the
+    Section IV recurrence in block form) against the oracle, ragged last
+    panel; configuration 0 is the default the other tests run."""
+    torch = torch_cuda()
+    from paper_1111_4144_amd import api
+    api.autotune_clear()
+    try:
+        for n, dt, prec in [(200, np.float64, "plain"), (333, np.float32, "plain"),
+                            (333, np.float32, "mixed")]:
+            tdt = torch.float64 if dt == np.float64 else torch.float32
+            api.tune_set(tdt, n, cfg, precision=prec)
+            assert api.tuned_engine(tdt, n, precision=prec) == cfg
+            a = I.large_spd(n, seed=77 + n, top=1e3)
+            ref, _ = O.inv_prop(a.astype(dt).astype(np.float64))
+            x = api.inverse(torch.from_numpy(a.astype(dt)).cuda(), precision=prec).cpu().numpy()
+            tol = TOL_FP64 if dt == np.float64 else TOL_FP32
+            err = float(rel_err(x.astype(np.float64), ref))
+            assert err <= tol * 1e3, (cfg, n, prec, err)
+    finally:
+        api.autotune_clear()

@@ -81,3 +81,86 @@ def test_every_engine_keeps_parity(n, dt, prec):
             assert_within(x, ref, a, TOL_FP32, "engine %d, %s %s order %d" % (e, dt, prec, n))
     finally:
         api.autotune_clear()
+
+
+def test_autotune_large_records_a_configuration(tmp_path):
+    """Tuning a large order records one of the configurations for its bucket,
+    keeps parity through it, and is loaded from the cache by a second run."""
+    torch = torch_cuda()
+    from paper_1111_4144_amd import api
+    cache = tmp_path / "tune_large.txt"
+    api.autotune_clear()
+    try:
+        assert api.autotune(torch.float32, precision="mixed", orders=(520, 520), cache=cache) == 1
+        cfg = api.tuned_engine(torch.float32, 520, precision="mixed")
+        assert 0 <= cfg <= 4
+        assert api.tuned_engine(torch.float32, 600, precision="mixed") == cfg   # same bucket
+        a = I.large_spd(520, seed=8, top=1e3, dtype=np.float32).astype(np.float64)
+        ref, _ = O.inv_prop(a)
+        x = api.inverse(torch.from_numpy(a.astype(np.float32)).cuda(), precision="mixed")
+        err = float(np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref))
+        assert err <= TOL_FP32 * 1e3, (cfg, err)
+        api.autotune_clear()
+        assert api.autotune(torch.float32, precision="mixed", orders=(520, 520), cache=cache) == 0
+        assert api.tuned_engine(torch.float32, 520, precision="mixed") == cfg
+    finally:
+        api.autotune_clear()
+
+
+@pytest.mark.parametrize("prec,ns", [("plain", 0), ("mixed", 1)])
+def test_autotune_varlen_edges_keep_parity(prec, ns):
+    """The uneven-batch tuner returns one of its bucket edges; every edge
+    (pinned) keeps parity with the oracle on a batch that spans all sizes."""
+    torch = torch_cuda()
+    from paper_1111_4144_amd import api
+    packed, sizes, offs = I.varlen_spd(1500, seed=31)
+    P = torch.from_numpy(packed).cuda()
+    S = torch.from_numpy(sizes).cuda()
+    OF = torch.from_numpy(offs).cuda()
+    xo, io = O.inv_prop_varlen(packed, sizes, offs)
+    api.autotune_clear()
+    try:
+        edge = api.autotune_varlen(P, S, OF, n_max=64, precision=prec, ns_steps=ns)
+        assert edge in (17, 25, 33)
+        assert api.tuned_engine(torch.float32, 0, precision=prec) == edge
+        for e in (17, 25, 33):
+            api.tune_set(torch.float32, 0, e, precision=prec)
+            x, info = api.inverse_varlen(P, S, OF, n_max=64, precision=prec, ns_steps=ns,
+                                         return_info=True)
+            x = x.cpu().numpy()
+            assert np.array_equal(info.cpu().numpy(), io)
+            for b in range(0, 1500, 5):
+                n, o = int(sizes[b]), int(offs[b])
+                xm = x[o:o + n * n].reshape(n, n).astype(np.float64)
+                ref = xo[o:o + n * n].reshape(n, n)
+                err = np.linalg.norm(xm - ref) / np.linalg.norm(ref)
+                kap = O.kappa2(packed[o:o + n * n].reshape(n, n).astype(np.complex128))
+                assert err <= TOL_FP32 * kap, (e, b, n, err)
+    finally:
+        api.autotune_clear()
+
+
+def test_refinement_three_product_form_matches_four_product_form():
+    """The MFMA refinement forms complex products with three real products
+    ((Ar + Ai)(Xr + Xi) among them) where the lane form uses four; the extra
+    FP32 rounding sits in the small correction X E and must not show in the
+    refined inverse: on the same 16 x 16 MIMO matrices the three-product
+    engines (5, 6) stay within twice the four-product engine's (4) error
+    against the oracle, in the median and the maximum."""
+    torch = torch_cuda()
+    from paper_1111_4144_amd import api
+    a = I.mimo(16, 2000, seed=4711)
+    ref, _ = O.inv_prop(a)
+    A = torch.from_numpy(a).cuda()
+    errs = {}
+    api.autotune_clear()
+    try:
+        for e in (4, 5, 6):
+            api.tune_set("c64", 16, e, precision="mixed")
+            x = api.inverse(A, precision="mixed", ns_steps=1).cpu().numpy()
+            errs[e] = np.linalg.norm(x - ref, axis=(1, 2)) / np.linalg.norm(ref, axis=(1, 2))
+    finally:
+        api.autotune_clear()
+    for e in (5, 6):
+        assert np.median(errs[e]) <= 2 * np.median(errs[4]), (e, np.median(errs[e]), np.median(errs[4]))
+        assert errs[e].max() <= 2 * errs[4].max(), (e, errs[e].max(), errs[4].max())
