@@ -38,6 +38,16 @@ CI_D V g16_make(float r, float i)
     else return r;
 }
 
+// Orders the LDS accesses of one wave across its lanes (a workgroup of one
+// wave needs no workgroup barrier): a wavefront-scope release fence, a wave
+// barrier that no instruction is moved across, and an acquire fence.
+CI_D void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // One Newton-Schulz step on the staged matrix A (Hermitian, full) and X
 // (Hermitian, full), in place on X.  Whole wave.
 template <class V>
@@ -99,10 +109,10 @@ CI_D void g16_ns_step(const V* __restrict__ As, V* __restrict__ Xs, int lane)
         const V xo = Xs[i * G16_LD + c];
         xn[v] = g16_make<V>(g16_re(xo) + fr[v], C ? g16_im(xo) + fi[v] : 0.f);
     }
-    // The workgroup is this one wave, whose LDS accesses complete in program
-    // order: the reads of X above precede these writes for every lane, and the
-    // writes precede any later read.  No workgroup barrier is needed, so the
-    // compiler may overlap the next matrix's loads with this one's products.
+    // Every lane's reads of X above precede any lane's writes below, and the
+    // writes precede later reads (the next step, the store): both orders are
+    // made explicit at wavefront scope.
+    wave_sync();
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int i = 4 * g + v;
@@ -112,6 +122,7 @@ CI_D void g16_ns_step(const V* __restrict__ As, V* __restrict__ Xs, int lane)
             Xs[c * G16_LD + i] = cj(xn[v]);
         }
     }
+    wave_sync();
 }
 
 #ifndef CI_G16_WAVES

@@ -12,7 +12,8 @@
 //
 // One lane per matrix.  The integer work is long (int64 products and
 // divisions), so a lane keeps its factor and its Y in LDS, entry-major with
-// the block's 16 lanes interleaved (conflict-free), and the block is small.
+// the block's 16 lanes interleaved (conflict-free), and the block is small;
+// its LDS is sized for order 8 or 16, whichever holds n.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -23,9 +24,10 @@ namespace ci {
 namespace {
 
 constexpr int QL = 16;                      // lanes (matrices) per block
-constexpr int QN = 16;                      // largest order
-constexpr int QE = QN * (QN + 1) / 2;       // packed upper entries
+constexpr int QN_MAX = 16;                  // largest order
 
+// packed index of (i, j), i <= j, of the upper triangle of order QN
+template <int QN>
 __device__ __forceinline__ int qp(int i, int j) { return i * QN - (i * (i - 1)) / 2 + (j - i); }
 
 // floor(sqrt(v)), 0 <= v < 2^31: a double estimate corrected to the exact floor
@@ -54,11 +56,15 @@ __device__ __forceinline__ int64_t q_sat(int64_t v, int64_t lim, int& sat)
     return v;
 }
 
+// QN: the order the block's LDS is sized for (8 or 16; n <= QN), so that
+// blocks of small orders take a quarter of the LDS and more of them reside.
+template <int QN>
 __global__ void __launch_bounds__(QL)
 k_inv_q15(const int16_t* __restrict__ a, int64_t stride, int16_t* __restrict__ x,
           int32_t* __restrict__ xexp, int32_t* __restrict__ sat_out, int32_t* __restrict__ info,
           int64_t batch, int n)
 {
+    constexpr int QE = QN * (QN + 1) / 2;   // packed upper entries
     __shared__ int32_t Rr[QE * QL], Ri[QE * QL];
     __shared__ int64_t Yr[QE * QL], Yi[QE * QL];
     const int l = threadIdx.x;
@@ -66,10 +72,10 @@ k_inv_q15(const int16_t* __restrict__ a, int64_t stride, int16_t* __restrict__ x
     if (b >= batch) return;                 // lanes share no LDS entries
     const int16_t* ab = a + b * stride * 2;
     int16_t* xb = x + b * stride * 2;
-#define RR(i, j) Rr[qp(i, j) * QL + l]
-#define RI(i, j) Ri[qp(i, j) * QL + l]
-#define YR(i, j) Yr[qp(i, j) * QL + l]
-#define YI(i, j) Yi[qp(i, j) * QL + l]
+#define RR(i, j) Rr[qp<QN>(i, j) * QL + l]
+#define RI(i, j) Ri[qp<QN>(i, j) * QL + l]
+#define YR(i, j) Yr[qp<QN>(i, j) * QL + l]
+#define YI(i, j) Yi[qp<QN>(i, j) * QL + l]
     constexpr int64_t QMAX = 32767, YLIM = ((int64_t)1 << 40) - 1;
     int sat = 0, fail = 0;
 
@@ -163,9 +169,13 @@ hipError_t launch_inv_q15(const int16_t* a, int64_t stride, int16_t* x, int32_t*
                           int32_t* sat, int32_t* info, int64_t batch, int n, hipStream_t s)
 {
     if (batch <= 0 || n <= 0) return hipSuccess;
-    if (n > QN) return hipErrorNotSupported;
-    hipLaunchKernelGGL(k_inv_q15, dim3((unsigned)((batch + QL - 1) / QL)), dim3(QL), 0, s, a,
-                       stride, x, xexp, sat, info, batch, n);
+    if (n > QN_MAX) return hipErrorNotSupported;
+    const dim3 grid((unsigned)((batch + QL - 1) / QL)), block(QL);
+    if (n <= 8)
+        hipLaunchKernelGGL(k_inv_q15<8>, grid, block, 0, s, a, stride, x, xexp, sat, info, batch, n);
+    else
+        hipLaunchKernelGGL(k_inv_q15<16>, grid, block, 0, s, a, stride, x, xexp, sat, info, batch,
+                           n);
     return hipGetLastError();
 }
 

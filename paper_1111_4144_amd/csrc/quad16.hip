@@ -44,13 +44,6 @@ constexpr int Q16_TILE = CI_Q16_TILE;     // matrices per Newton-Schulz / store 
 // packed index of (i, j), i <= j, row-major upper triangle of order 16
 CI_D int q16_pk(int i, int j) { return i * (31 - i) / 2 + j; }
 
-CI_D void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // One Newton-Schulz step for one staged matrix: A from the packed upper
 // triangle (a_ck = conj(a_kc) for c > k), X full in the padded tile, in place.
 // aoff / aconj: the lane's four packed offsets of a_{c, 4t+g} and whether the
