@@ -541,7 +541,14 @@ def main():
     del x8, x16
 
     if not args.no_extras:
-        # plain FP64 on the same matrices (complex128), the speedup baseline
+        # plain FP64 on the same matrices (complex128), the speedup baseline; its
+        # engines are measured and chosen on this device like the mixed ones
+        ptuned = {}
+        for n in (8, 16):
+            if not args.no_tune:
+                api.autotune(torch.complex128, precision="plain", orders=(n, n),
+                             batch=COUNT_PER_ORDER)
+            ptuned[n] = api.tuned_engine(torch.complex128, n, precision="plain")
         B8 = A8.to(torch.complex128)
         B16 = A16.to(torch.complex128)
         Y8 = torch.empty_like(B8)
@@ -554,6 +561,12 @@ def main():
         details["plain_fp64_inv_per_s"] = total / (p_ms / 1e3)
         details["plain_fp64_max_rel_err_vs_lapack"] = max(pe8, pe16)
         details["speedup_mixed_vs_plain_fp64"] = p_ms / step_ms
+        # per order: c128 moves 2 x 16 bytes per entry (A in, X out)
+        for n, ms_n in ((8, p8), (16, p16)):
+            details["plain_c128_%dx%d_launch_ms" % (n, n)] = ms_n
+            details["plain_c128_%dx%d_hbm_frac" % (n, n)] = \
+                COUNT_PER_ORDER * n * n * 32 / (ms_n / 1e3) / HBM_PEAK
+            details["plain_c128_tuned_engine_%dx%d" % (n, n)] = ptuned[n]
         del B8, B16, Y8, Y16
         # mixed precision without refinement and plain FP32, for context
         z_ms, _ = _time_loop(torch, [lambda: api.inverse(A8, precision="mixed", ns_steps=0, out=X8),

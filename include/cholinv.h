@@ -346,7 +346,9 @@ const char* chol_version(void);
  * Newton-Schulz step on MFMA, mixed precision only; 6 four-lane groups with
  * sixteen matrices per wave, orders 9..16, CI_F32 / CI_C64, the refinement
  * on MFMA, the built-in choice for CI_C64 orders 9..16 and for CI_F32 orders
- * 9..16 in mixed precision).  The choice depends on
+ * 9..16 in mixed precision; 7 eight-lane groups for CI_F64 / CI_C128 in plain
+ * precision, one column per lane up to order 8 and two above).  The choice
+ * depends on
  * the device, so it is measured, not fixed.
  *
  * chol_autotune times every candidate engine of (dtype, opts) for each order

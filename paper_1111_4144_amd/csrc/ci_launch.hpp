@@ -53,7 +53,8 @@ enum {
     ENG_TPM_PERSIST = 3,
     ENG_GROUP_LANES = 4,
     ENG_GROUP_MFMA = 5,
-    ENG_QUAD16 = 6
+    ENG_QUAD16 = 6,
+    ENG_GROUP8 = 7
 };
 // Recorded choice for (dtype, mixed, method, n), ENG_DEFAULT if none.
 int tuned_engine(int dtype, int mixed, int method, int n);
@@ -108,6 +109,10 @@ hipError_t launch_group_c64(int n, int op, int method, int mixed, const BatchArg
 hipError_t launch_group_c128(int n, int op, int method, int mixed, const BatchArgs& p, hipStream_t s);
 // Four lanes per matrix, sixteen matrices per wave (orders <= 16, float and
 // complex float, inversion only; mixed precision refines on MFMA).
+// Eight lanes per matrix (orders <= 16, double and complex double, plain
+// precision, inversion only).
+hipError_t launch_group8(int dtype, int n, int op, int method, int mixed, const BatchArgs& p,
+                         hipStream_t s);
 hipError_t launch_quad16(int dtype, int n, int op, int method, int mixed, const BatchArgs& p,
                          hipStream_t s);
 // LDS-resident group kernels for orders 17..64 (real) / 17..32 (complex).

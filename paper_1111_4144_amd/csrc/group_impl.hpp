@@ -140,6 +140,11 @@ template <int G> CI_D cd bcr(cd v, int k) { return cd{bcr<G>(v.re, k), bcr<G>(v.
 
 template <class V>
 CI_D V sel(bool c, V a, V b) { return c ? a : b; }
+// Complex values select part by part: a conditional on whole structs becomes
+// a copy from a selected address, which keeps the arrays involved in scratch
+// memory instead of registers.
+CI_D cf sel(bool c, cf a, cf b) { return cf{c ? a.re : b.re, c ? a.im : b.im}; }
+CI_D cd sel(bool c, cd a, cd b) { return cd{c ? a.re : b.re, c ? a.im : b.im}; }
 
 // Sum over the 16 lanes of a DPP row, every lane getting the total: quad
 // exchanges (xor 1, xor 2), then row_half_mirror (quad 0 <-> 1, 2 <-> 3) and
@@ -240,7 +245,7 @@ CI_D int group_core(V (&M)[S][NB], P (&piv)[S], typename vt<V>::real (&dall)[NB]
             const V u = M[s][i];
             const V r = scal(u, sinv);
             wv[s] = (METHOD == 0) ? r : u;
-            M[s][i] = (j > i) ? r : ((j == i) ? mk<V>(rdiag) : M[s][i]);
+            M[s][i] = sel(j > i, r, sel(j == i, mk<V>(rdiag), M[s][i]));
             const P dlt = dot_re<P>(r, wv[s]);
             piv[s] = (j > i) ? piv[s] - dlt : piv[s];
         }
@@ -290,7 +295,7 @@ CI_D int group_core(V (&M)[S][NB], P (&piv)[S], typename vt<V>::real (&dall)[NB]
 #pragma unroll
             for (int j = i + 1; j < NB; ++j) {
                 const V v = bc<G>(xnew[j / G], j % G);
-                M[si][j] = (q == qi) ? cj(v) : M[si][j];
+                M[si][j] = sel(q == qi, cj(v), M[si][j]);
             }
             // (c) x_ii = s_i (s_i - sum_{k>i} r_ik conj(x_ik)) on the owner; row i
             // of R is still in place (it is replaced only below)
@@ -300,7 +305,7 @@ CI_D int group_core(V (&M)[S][NB], P (&piv)[S], typename vt<V>::real (&dall)[NB]
                 // (its xnew): one local product each, summed across the row
                 V prod = mk<V>(R(0));
                 madd(prod, M[0][i], cj(xnew[0]));
-                prod = (q > i) ? prod : mk<V>(R(0));
+                prod = sel(q > i, prod, mk<V>(R(0)));
                 d = add(d, neg(row_sum16v(prod)));
             } else if constexpr (G == 4) {
                 // the same with four columns per lane: local products over the
@@ -311,7 +316,7 @@ CI_D int group_core(V (&M)[S][NB], P (&piv)[S], typename vt<V>::real (&dall)[NB]
                     if (s * G + G - 1 > i) {
                         V t = mk<V>(R(0));
                         madd(t, M[s][i], cj(xnew[s]));
-                        prod = add(prod, (s * G + q > i) ? t : mk<V>(R(0)));
+                        prod = add(prod, sel(s * G + q > i, t, mk<V>(R(0))));
                     }
                 }
                 d = add(d, neg(quad_sumv(prod)));
@@ -332,7 +337,7 @@ CI_D int group_core(V (&M)[S][NB], P (&piv)[S], typename vt<V>::real (&dall)[NB]
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 const int j = s * G + q;
-                M[s][i] = (j > i) ? xnew[s] : ((j == i) ? d : M[s][i]);
+                M[s][i] = sel(j > i, xnew[s], sel(j == i, d, M[s][i]));
             }
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -367,11 +372,12 @@ CI_D void group_matrix(const V* __restrict__ a, int64_t lda, int n, V* x, int64_
         for (int k = 0; k < NB; ++k) {
             V v = mk<V>(R(k == j ? 1 : 0));
             if (valid && j < n && k < n) {
-                v = (k <= j) ? a[k * lda + j] : cj(a[j * lda + k]);
+                if (k <= j) v = a[k * lda + j];      // one load, from the upper triangle
+                else v = cj(a[j * lda + k]);
                 if (k == j) v = realpart_only(v);
             }
             if constexpr (MIXED) Af[s][k] = v;
-            M[s][k] = (k <= j) ? v : mk<V>(R(0));
+            M[s][k] = sel(k <= j, v, mk<V>(R(0)));
             if (k == j) piv[s] = (P)re(v);
         }
     }
@@ -453,7 +459,7 @@ CI_D void group_matrix(const V* __restrict__ a, int64_t lda, int n, V* x, int64_
 #pragma unroll
                     for (int i = 0; i < NB; ++i) {
                         const int j = s * G + q;
-                        M[s][i] = (i == j) ? realpart_only(upd[s][i]) : upd[s][i];
+                        M[s][i] = sel(i == j, realpart_only(upd[s][i]), upd[s][i]);
                     }
             }
         }
@@ -468,7 +474,7 @@ CI_D void group_matrix(const V* __restrict__ a, int64_t lda, int n, V* x, int64_
 #pragma unroll
                     for (int i = 0; i < NB; ++i) {
                         if (i < n && i <= j) {
-                            const V v = fail ? nan_value<V>() : M[s][i];
+                            const V v = sel(fail != 0, nan_value<V>(), M[s][i]);
                             x[i * ldx + j] = v;
                             if (fill && i < j) x[j * ldx + i] = cj(v);
                         }

@@ -4,8 +4,9 @@
 // matrix kernels with direct loads, one-shot LDS staging or persistent
 // staging (orders up to the per-type register limit), the 16-lane group
 // kernels with the Newton-Schulz step on the lane groups or on MFMA (mixed
-// precision), and the 4-lane groups with sixteen matrices per wave (orders
-// 9..16, float and complex float).  chol_autotune times every candidate for each order of a range
+// precision), the 4-lane groups with sixteen matrices per wave (orders
+// 9..16, float and complex float) and the 8-lane groups of the FP64 types
+// (plain precision).  chol_autotune times every candidate for each order of a range
 // on a synthetic batch on the caller's device and stream and records the
 // fastest; run_small consults the record.  Choices can be persisted in a text
 // cache keyed by the device (name and compute-unit count), so later processes
@@ -96,6 +97,7 @@ int candidates(int dtype, int mixed, int n, int* out)
         out[k++] = ENG_GROUP_LANES;
         if (mixed && (dtype == DT_F32 || dtype == DT_C64)) out[k++] = ENG_GROUP_MFMA;
         if (n >= 9 && (dtype == DT_F32 || dtype == DT_C64)) out[k++] = ENG_QUAD16;
+        if (!mixed && (dtype == DT_F64 || dtype == DT_C128)) out[k++] = ENG_GROUP8;
     }
     return k;
 }
@@ -124,7 +126,7 @@ bool load_cache(const char* path, const std::string& dev, int dtype, int mixed, 
             have[0] = true;
             continue;
         }
-        if (e < ENG_DEFAULT || e > ENG_QUAD16) continue;
+        if (e < ENG_DEFAULT || e > ENG_GROUP8) continue;
         g_table[dtype][mixed][method][n] = e;
         have[n] = true;
     }
@@ -152,6 +154,7 @@ hipError_t launch_engine(int engine, int dtype, int n, int op, int method, int m
     case ENG_GROUP_LANES: p.ns_engine = NS_ENGINE_LANES; return launch_group(dtype, n, op, method, mixed, p, s);
     case ENG_GROUP_MFMA: p.ns_engine = NS_ENGINE_MFMA; return launch_group(dtype, n, op, method, mixed, p, s);
     case ENG_QUAD16: return launch_quad16(dtype, n, op, method, mixed, p, s);
+    case ENG_GROUP8: return launch_group8(dtype, n, op, method, mixed, p, s);
     default: return hipErrorInvalidValue;
     }
 }

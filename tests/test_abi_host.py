@@ -121,6 +121,10 @@ def test_tune_set_validates_engines():
         assert lib.chol_tune_set(L.CI_C64, ctypes.byref(mixed), 8, 6) == -4     # order < 9
         assert lib.chol_tune_set(L.CI_C64, ctypes.byref(plain), 16, 5) == -4    # MFMA needs mixed
         assert lib.chol_tune_set(L.CI_C64, ctypes.byref(mixed), 16, 9) == -4    # no such engine
+        assert lib.chol_tune_set(L.CI_C128, ctypes.byref(plain), 16, 7) == 0    # eight lanes
+        assert lib.chol_tune_set(L.CI_F64, ctypes.byref(plain), 5, 7) == 0
+        assert lib.chol_tune_set(L.CI_C64, ctypes.byref(plain), 16, 7) == -4    # FP64 types only
+        assert lib.chol_tune_set(L.CI_F32, ctypes.byref(mixed), 16, 7) == -4
         assert lib.chol_tune_set(L.CI_C64, ctypes.byref(mixed), 17, 4) == -3
         assert lib.chol_tune_set(7, ctypes.byref(mixed), 16, 4) == -1
     finally:

@@ -8,7 +8,7 @@ import pytest
 
 import oracle as O
 from paper_1111_4144_amd import inputs as I
-from tests.helpers import TOL_FP32, assert_within, torch_cuda
+from tests.helpers import TOL_FP32, TOL_FP64, assert_within, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -79,6 +79,31 @@ def test_every_engine_keeps_parity(n, dt, prec):
             x = api.inverse(torch.from_numpy(a).cuda(), precision=prec).cpu().numpy()
             assert np.array_equal(x, np.conj(np.swapaxes(x, -1, -2)))
             assert_within(x, ref, a, TOL_FP32, "engine %d, %s %s order %d" % (e, dt, prec, n))
+    finally:
+        api.autotune_clear()
+
+
+@pytest.mark.parametrize("dt", ["c128", "f64"])
+@pytest.mark.parametrize("n", [1, 3, 8, 9, 13, 16])
+@pytest.mark.parametrize("method", ["chol", "ldl"])
+def test_eight_lane_engine_keeps_parity(n, dt, method):
+    """The eight-lanes-per-matrix FP64 engine (one column per lane up to order
+    8, two above), pinned with tune_set, against the oracle on a batch whose
+    last wave is ragged; the sixteen-lane engine on the same batch for
+    comparison."""
+    torch = torch_cuda()
+    from paper_1111_4144_amd import api
+    cplx = dt == "c128"
+    a = I.random_hpd(np.random.default_rng(300 + n), 1001, n, shift=0.5, complex_=cplx,
+                     dtype=np.complex128 if cplx else np.float64)
+    ref, _ = O.inv_prop(a, method=method)
+    api.autotune_clear()
+    try:
+        for e in (7, 4):
+            api.tune_set(dt, n, e, method=method)
+            x = api.inverse(torch.from_numpy(a).cuda(), method=method).cpu().numpy()
+            assert np.array_equal(x, np.conj(np.swapaxes(x, -1, -2)))
+            assert_within(x, ref, a, TOL_FP64, "engine %d, %s %s order %d" % (e, dt, method, n))
     finally:
         api.autotune_clear()
 
