@@ -379,7 +379,7 @@ int chol_tuned_engine(int dtype, const ci_opts* opts, int n);
  * order, or 0 for the built-in choice) for (dtype, opts precision/method,
  * order n, 1..16) without measuring, e.g. a choice read from a tuning file or
  * one a test wants to exercise.  n > CI_SMALL_NMAX records a large-order
- * configuration 0..4 for n's bucket; n = 0 records the uneven-batch bucket
+ * configuration 0..5 for n's bucket; n = 0 records the uneven-batch bucket
  * edge (0, 17, 25 or 33).  Returns 0, or -k for an invalid argument k (-4:
  * the engine cannot invert this combination). */
 int chol_tune_set(int dtype, const ci_opts* opts, int n, int engine);
@@ -394,6 +394,8 @@ int chol_tune_set(int dtype, const ci_opts* opts, int n, int engine);
  *   1, 2 the same aiming at 256 / 1024 workgroups
  *   3 diagonal blocks by the row-by-row Crout recurrence
  *   4 the Section IV recurrence in block form for the inverse
+ *   5 configuration 0 with the long unsplit products (at least 256 tiles,
+ *     K >= 512) on 256 x 128 workgroup tiles instead of 128 x 128
  * Returns 1 when it measured, 0 when the cache had the answer.  Later
  * chol_inverse / chol_factor calls of that bucket use the record. */
 

@@ -9,8 +9,10 @@
 // are exact).  uplo = 1 computes and writes only entries with column >= row:
 // the upper half of a symmetric product; only tiles that meet it are launched.
 //
-// Tiling: a workgroup of 256 lanes (4 waves, 2 x 2) owns a 128 x 128 tile of
-// C; each wave a 64 x 64 sub-tile made of 4 x 4 MFMA blocks of 16 x 16
+// Tiling: a workgroup of WM x WN waves owns a (64 WM) x (64 WN) tile of C
+// (128 x 128 with 2 x 2 waves; 256 x 128 with 4 x 2 for long products, a
+// quarter fewer operand bytes per flop); each wave a 64 x 64
+// sub-tile made of 4 x 4 MFMA blocks of 16 x 16
 // (v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64).  K advances by BK per
 // stage (32 for FP32, 16 for FP64).  Global loads are 16-byte vectors along
 // each operand's contiguous dimension; an operand is kept in LDS in the same
@@ -54,33 +56,37 @@ struct GemmArgs {
     int tri = 0;
 };
 
+// the small tile: 2 x 2 waves, 128 x 128
 constexpr int GT_M = 128, GT_N = 128;
-constexpr int G_THREADS = 256;
 template <class T> constexpr int G_BK = sizeof(T) == 4 ? 32 : 16;
 template <class T> constexpr int G_PAD = 16 / (int)sizeof(T);          // 16 bytes per LDS row
 
-// LDS elements of one operand buffer in either orientation
-template <class T, bool KC> constexpr int g_lds_elems()
+// LDS elements of one operand buffer of outer extent TO in either orientation
+template <class T, bool KC, int TO> constexpr int g_lds_elems()
 {
-    return KC ? GT_M * (G_BK<T> + G_PAD<T>) : G_BK<T> * (GT_M + G_PAD<T>);
+    return KC ? TO * (G_BK<T> + G_PAD<T>) : G_BK<T> * (TO + G_PAD<T>);
 }
-template <class T> constexpr size_t gemm_lds_bytes()
+template <class T, int TO> constexpr int g_lds_max()
 {
-    constexpr int a = g_lds_elems<T, true>() > g_lds_elems<T, false>() ? g_lds_elems<T, true>()
-                                                                       : g_lds_elems<T, false>();
-    return (size_t)4 * a * sizeof(T);          // 2 operands x 2 buffers
+    return g_lds_elems<T, true, TO>() > g_lds_elems<T, false, TO>() ? g_lds_elems<T, true, TO>()
+                                                                     : g_lds_elems<T, false, TO>();
+}
+// LDS of a (64 WM) x (64 WN) tile: 2 operands x 2 buffers
+template <class T, int WM, int WN> constexpr size_t gemm_lds_bytes()
+{
+    return (size_t)2 * (g_lds_max<T, 64 * WM>() + g_lds_max<T, 64 * WN>()) * sizeof(T);
 }
 
 // One operand: outer extent O (M or N), K, source pointer / leading dimension,
-// KC = k contiguous in memory.  Staging registers hold NV vectors of VEC
-// source elements per lane.
-template <class T, class TS, bool KC>
+// KC = k contiguous in memory, TO the tile's outer extent, NT the workgroup's
+// lanes.  Staging registers hold NV vectors of VEC source elements per lane.
+template <class T, class TS, bool KC, int TO, int NT>
 struct GOperand {
     static constexpr int BK = G_BK<T>;
     static constexpr int VEC = 16 / (int)sizeof(TS);
-    static constexpr int NV = GT_M * BK / VEC / G_THREADS;
-    static constexpr int LDR = KC ? BK + G_PAD<T> : GT_M + G_PAD<T>;   // LDS row length
-    static_assert(NV >= 1 && (GT_M * BK) % (VEC * G_THREADS) == 0, "tile / vector split");
+    static constexpr int NV = TO * BK / VEC / NT;
+    static constexpr int LDR = KC ? BK + G_PAD<T> : TO + G_PAD<T>;   // LDS row length
+    static_assert(NV >= 1 && (TO * BK) % (VEC * NT) == 0, "tile / vector split");
 
     const TS* src;
     int64_t ld;
@@ -92,10 +98,10 @@ struct GOperand {
     {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            const int e = tid + G_THREADS * v;
+            const int e = tid + NT * v;
             int o, k;
             if constexpr (KC) { o = e / (BK / VEC); k = (e % (BK / VEC)) * VEC; }
-            else { k = e / (GT_M / VEC); o = (e % (GT_M / VEC)) * VEC; }
+            else { k = e / (TO / VEC); o = (e % (TO / VEC)) * VEC; }
             const int go = o0 + o, gk = k0 + k;
             const bool full = KC ? (go < O && gk + VEC <= K) : (gk < K && go + VEC <= O);
             if (vec_ok && full) {
@@ -120,10 +126,10 @@ struct GOperand {
     {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            const int e = tid + G_THREADS * v;
+            const int e = tid + NT * v;
             int o, k;
             if constexpr (KC) { o = e / (BK / VEC); k = (e % (BK / VEC)) * VEC; }
-            else { k = e / (GT_M / VEC); o = (e % (GT_M / VEC)) * VEC; }
+            else { k = e / (TO / VEC); o = (e % (TO / VEC)) * VEC; }
             T* q = KC ? L + o * LDR + k : L + k * LDR + o;
 #pragma unroll
             for (int c = 0; c < VEC; ++c) q[c] = (T)r[v][c];
@@ -145,11 +151,23 @@ struct GOperand {
     }
 };
 
+// Tiles of a TM x TN tiling that meet the upper triangle (column >= row):
+// row tile r starts at column tile (r TM) / TN.
+__device__ __host__ __forceinline__ int gemm_upper_tiles(int tiles_m, int tiles_n, int TM, int TN)
+{
+    int t = 0;
+    for (int r = 0; r < tiles_m; ++r) {
+        const int c0 = r * TM / TN;
+        if (c0 < tiles_n) t += tiles_n - c0;
+    }
+    return t;
+}
+
 // Tile and K split of a workgroup: XCD-grouped (the hardware deals
 // workgroups round-robin over 8 XCDs; consecutive indices on one XCD get
 // neighbouring tiles), and for uplo only tiles that meet the upper triangle.
 __device__ __forceinline__ void gemm_tile(int bid, int nblocks, int ntiles, int tiles_n, int uplo,
-                                          int& bm, int& bn, int& split)
+                                          int TM, int TN, int& bm, int& bn, int& split)
 {
     int l = bid;
     if (nblocks % 8 == 0) l = (bid % 8) * (nblocks / 8) + bid / 8;
@@ -161,30 +179,32 @@ __device__ __forceinline__ void gemm_tile(int bid, int nblocks, int ntiles, int 
         return;
     }
     int r = 0, rem = l;
-    while (rem >= tiles_n - r) { rem -= tiles_n - r; ++r; }
+    while (rem >= tiles_n - r * TM / TN) { rem -= tiles_n - r * TM / TN; ++r; }
     bm = r;
-    bn = r + rem;
+    bn = r * TM / TN + rem;
 }
 
-// Two workgroups per CU (two waves per SIMD): the LDS of two fits, and the
-// FP64 accumulators alone take 128 registers, so the register budget must
-// be bounded for the second workgroup to be resident.
-template <class T, class TA, class TB, bool AKC, bool BKC>
-__global__ void __launch_bounds__(G_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+// Occupancy: the 2 x 2 tile runs two workgroups per CU (two waves per SIMD:
+// the LDS of two fits, and the FP64 accumulators alone take 128 registers,
+// so the register budget is bounded for the second workgroup to be
+// resident); the 4 x 2 tile one workgroup of eight waves (its LDS).
+template <class T, class TA, class TB, bool AKC, bool BKC, int WM, int WN>
+__global__ void __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(2)))
 k_gemm(GemmArgs p)
 {
     using Acc = typename mfma_acc<T>::type;
     constexpr int BK = G_BK<T>;
+    constexpr int TM = 64 * WM, TN = 64 * WN, NT = 64 * WM * WN;
     extern __shared__ __align__(16) unsigned char g_smem[];
-    constexpr int LA = g_lds_elems<T, AKC>(), LB = g_lds_elems<T, BKC>();
+    constexpr int LA = g_lds_elems<T, AKC, TM>(), LB = g_lds_elems<T, BKC, TN>();
     T* const La0 = reinterpret_cast<T*>(g_smem);
     T* const Lb0 = La0 + 2 * LA;
 
-    const int tiles_m = (p.M + GT_M - 1) / GT_M, tiles_n = (p.N + GT_N - 1) / GT_N;
-    const int ntiles = p.uplo ? tiles_n * (tiles_n + 1) / 2 : tiles_m * tiles_n;
+    const int tiles_m = (p.M + TM - 1) / TM, tiles_n = (p.N + TN - 1) / TN;
+    const int ntiles = p.uplo ? gemm_upper_tiles(tiles_m, tiles_n, TM, TN) : tiles_m * tiles_n;
     int bm, bn, split;
-    gemm_tile(blockIdx.x, gridDim.x, ntiles, tiles_n, p.uplo, bm, bn, split);
-    const int m0 = bm * GT_M, n0 = bn * GT_N;
+    gemm_tile(blockIdx.x, gridDim.x, ntiles, tiles_n, p.uplo, TM, TN, bm, bn, split);
+    const int m0 = bm * TM, n0 = bn * TN;
     int kb = split * p.kc;
     const int ke = min(p.K, kb + p.kc);
     if (p.tri & 1) kb = max(kb, m0);
@@ -195,11 +215,11 @@ k_gemm(GemmArgs p)
 
     const int tid = threadIdx.x;
     const int wave = tid / 64, lane = tid % 64;
-    const int wm = wave / 2, wn = wave % 2;
+    const int wm = wave / WN, wn = wave % WN;
     const int lg = lane / 16, lc = lane % 16;
 
-    using OA = GOperand<T, TA, AKC>;
-    using OB = GOperand<T, TB, BKC>;
+    using OA = GOperand<T, TA, AKC, TM, NT>;
+    using OB = GOperand<T, TB, BKC, TN, NT>;
     OA opa;
     opa.src = Ap;
     opa.ld = p.lda; opa.O = p.M; opa.K = K; opa.o0 = m0;
@@ -272,11 +292,12 @@ k_gemm(GemmArgs p)
             }
 }
 
-template <class T, class TA, class TB, bool AKC, bool BKC>
-static hipError_t gemm_launch_t(const GemmArgs& p, int blocks, hipStream_t s)
+template <class T, class TA, class TB, bool AKC, bool BKC, int WM, int WN>
+static hipError_t gemm_launch_t(const GemmArgs& p, hipStream_t s)
 {
-    auto kern = k_gemm<T, TA, TB, AKC, BKC>;
-    constexpr size_t smem = gemm_lds_bytes<T>();
+    auto kern = k_gemm<T, TA, TB, AKC, BKC, WM, WN>;
+    constexpr size_t smem = gemm_lds_bytes<T, WM, WN>();
+    constexpr int TM = 64 * WM, TN = 64 * WN;
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void*)kern,
@@ -284,25 +305,46 @@ static hipError_t gemm_launch_t(const GemmArgs& p, int blocks, hipStream_t s)
         if (e != hipSuccess) return e;
         attr = true;
     }
-    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(G_THREADS), smem, s, p);
+    const int tm = (p.M + TM - 1) / TM, tn = (p.N + TN - 1) / TN;
+    const int blocks = (p.uplo ? gemm_upper_tiles(tm, tn, TM, TN) : tm * tn) * p.splits;
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * WM * WN), smem, s, p);
     return hipGetLastError();
+}
+
+// Whether a product takes the 256 x 128 tile: a plain (not split) product
+// with at least one such tile per compute unit and a long K range, when the
+// large-order configuration asks for it (set per thread; off by default:
+// measured at N = 8192 it gained 4% on the refinement's FP64 residual and
+// lost 3-7% on X = M M^T).
+static thread_local bool g_gemm_big = false;
+inline bool gemm_big_tile(const GemmArgs& p)
+{
+    if (!g_gemm_big || p.splits > 1 || p.K < 512) return false;
+    const int tm = (p.M + 255) / 256, tn = (p.N + 127) / 128;
+    const int tiles = p.uplo ? gemm_upper_tiles(tm, tn, 256, 128) : tm * tn;
+    return tiles >= 256;
+}
+
+template <class T, class TA, class TB, int WM, int WN>
+static hipError_t gemm_launch_w(const GemmArgs& q, hipStream_t s)
+{
+    // A is k-contiguous when not transposed; B is k-contiguous when transposed
+    if (!q.transA && q.transB) return gemm_launch_t<T, TA, TB, true, true, WM, WN>(q, s);
+    if (!q.transA && !q.transB) return gemm_launch_t<T, TA, TB, true, false, WM, WN>(q, s);
+    if (q.transA && q.transB) return gemm_launch_t<T, TA, TB, false, true, WM, WN>(q, s);
+    return gemm_launch_t<T, TA, TB, false, false, WM, WN>(q, s);
 }
 
 template <class T, class TA, class TB>
 static hipError_t gemm_launch(const GemmArgs& p, hipStream_t s)
 {
     if (p.M <= 0 || p.N <= 0) return hipSuccess;
-    const int tm = (p.M + GT_M - 1) / GT_M, tn = (p.N + GT_N - 1) / GT_N;
-    if (p.uplo && tm != tn) return hipErrorInvalidValue;
+    if (p.uplo && p.M != p.N) return hipErrorInvalidValue;
     if (p.splits < 1 || (p.splits > 1 && (p.kc <= 0 || p.beta != 0.0))) return hipErrorInvalidValue;
     GemmArgs q = p;
     if (q.splits == 1) q.kc = q.K;
-    const int blocks = (p.uplo ? tn * (tn + 1) / 2 : tm * tn) * q.splits;
-    // A is k-contiguous when not transposed; B is k-contiguous when transposed
-    if (!q.transA && q.transB) return gemm_launch_t<T, TA, TB, true, true>(q, blocks, s);
-    if (!q.transA && !q.transB) return gemm_launch_t<T, TA, TB, true, false>(q, blocks, s);
-    if (q.transA && q.transB) return gemm_launch_t<T, TA, TB, false, true>(q, blocks, s);
-    return gemm_launch_t<T, TA, TB, false, false>(q, blocks, s);
+    if (gemm_big_tile(q)) return gemm_launch_w<T, TA, TB, 4, 2>(q, s);
+    return gemm_launch_w<T, TA, TB, 2, 2>(q, s);
 }
 
 }  // namespace ci

@@ -796,8 +796,10 @@ static hipError_t gemm_splitk(int M, int N, int K, double alpha, const T* A, int
 //   inv     0 = blocked triangular inverse + X = M M^T, 1 = the Section IV
 //           recurrence in block form
 //   splitk  target workgroups of the split-K products
-struct LgCfg { int diag, inv, splitk; };
-static const LgCfg LG_CFGS[] = {{0, 0, 512}, {0, 0, 256}, {0, 0, 1024}, {1, 0, 512}, {0, 1, 512}};
+//   big     1 = long unsplit products take the 256 x 128 tile, 0 = 128 x 128 only
+struct LgCfg { int diag, inv, splitk, big; };
+static const LgCfg LG_CFGS[] = {{0, 0, 512, 0}, {0, 0, 256, 0}, {0, 0, 1024, 0},
+                                {1, 0, 512, 0}, {0, 1, 512, 0}, {0, 0, 512, 1}};
 constexpr int LG_NCFG = sizeof(LG_CFGS) / sizeof(LG_CFGS[0]);
 static thread_local LgCfg g_cfg = LG_CFGS[0];
 
@@ -1020,6 +1022,7 @@ static void lg_select(int cfg)
 {
     g_cfg = LG_CFGS[(cfg >= 0 && cfg < LG_NCFG) ? cfg : 0];
     g_splitk_target = g_cfg.splitk;
+    g_gemm_big = g_cfg.big != 0;
 }
 
 hipError_t large_factor(int dtype, int64_t n, void* a, int64_t lda, int32_t* info, void* work,

@@ -108,6 +108,32 @@ def test_kms_closed_form_full_size(n, dt, prec, ns):
     assert np.array_equal(x, x.T)
 
 
+@pytest.mark.parametrize("dt,prec,ns", [("f64", "plain", None), ("f32", "mixed", 1)])
+def test_wide_tile_products_match_small_tiles(dt, prec, ns):
+    """At n = 4096 the long unsplit products (X = M M^T, the refinement's
+    residual and update) take 256 x 128 tiles in configuration 5 and 128 x 128
+    tiles in the built-in configuration.  Each output entry's K sum runs in
+    the same order in both, so the inverses agree bit for bit; the closed form
+    bounds both."""
+    torch = torch_cuda()
+    from paper_1111_4144_amd import api
+    n, rho = 4096, 0.5
+    a = I.kms(n, rho, dtype=np.float64)
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    api.autotune_clear()
+    try:
+        api.tune_set(tdt, n, 0, precision=prec)
+        x0, i0 = _inverse(a, dt, prec, ns_steps=ns)
+        api.tune_set(tdt, n, 5, precision=prec)
+        x5, i5 = _inverse(a, dt, prec, ns_steps=ns)
+    finally:
+        api.autotune_clear()
+    assert i0 == 0 and i5 == 0
+    assert np.array_equal(x0, x5)
+    tol = TOL_FP64 if dt == "f64" else TOL_FP32
+    assert _fro_rel(x0, _kms_inverse(n, rho)) <= tol * ((1 + rho) / (1 - rho)) ** 2
+
+
 _LARGE_CACHE = {}
 
 
@@ -222,7 +248,7 @@ def test_large_mixed_refinement_improves():
     assert e1 < 0.5 * e0, (e0, e1)
 
 
-@pytest.mark.parametrize("cfg", [1, 2, 3, 4])
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4, 5])
 def test_large_configurations_vs_oracle(cfg):
     """Every large-order configuration (pinned with tune_set for the orders'
     bucket: split-K targets 256 / 1024, the row-by-row diagonal kernel, the

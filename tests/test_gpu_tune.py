@@ -118,7 +118,7 @@ def test_autotune_large_records_a_configuration(tmp_path):
     try:
         assert api.autotune(torch.float32, precision="mixed", orders=(520, 520), cache=cache) == 1
         cfg = api.tuned_engine(torch.float32, 520, precision="mixed")
-        assert 0 <= cfg <= 4
+        assert 0 <= cfg <= 5
         assert api.tuned_engine(torch.float32, 600, precision="mixed") == cfg   # same bucket
         a = I.large_spd(520, seed=8, top=1e3, dtype=np.float32).astype(np.float64)
         ref, _ = O.inv_prop(a)

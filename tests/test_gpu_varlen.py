@@ -32,9 +32,10 @@ def _check(xg, packed, sizes, offs, xo, tol, what):
 
 
 @pytest.mark.parametrize("dtype,prec,ns,method", [
-    (np.float32, "plain", 0, "chol"), (np.float32, "mixed", 1, "chol"),
-    (np.float32, "mixed", 2, "ldl"), (np.float64, "plain", 0, "chol"),
-    (np.float64, "plain", 0, "ldl")])
+    (np.float32, "plain", 0, "chol"), (np.float32, "plain", 0, "ldl"),
+    (np.float32, "mixed", 0, "chol"), (np.float32, "mixed", 0, "ldl"),
+    (np.float32, "mixed", 1, "chol"), (np.float32, "mixed", 2, "ldl"),
+    (np.float64, "plain", 0, "chol"), (np.float64, "plain", 0, "ldl")])
 def test_varlen_matches_oracle(dtype, prec, ns, method):
     t = torch_cuda()
     from paper_1111_4144_amd import api
@@ -91,6 +92,59 @@ def test_varlen_edge_cases():
     for b in (3, len(sizes) - 1):
         assert info2[b] == -1
         assert np.all(_unpack(x2, sizes, offs, b) == 5.0)
+
+
+@pytest.mark.parametrize("prec,method,fill", [("plain", "chol", True), ("plain", "ldl", False),
+                                               ("mixed", "chol", False)])
+def test_varlen_last_bucket_edge_cases(prec, method, fill):
+    """The last bucket of a real float batch without refinement: every order
+    33..64, a failing pivot near the end of an order-63 matrix, a failing first
+    pivot, and with fill_lower off the lower triangles left untouched."""
+    t = torch_cuda()
+    from paper_1111_4144_amd import api
+    sizes = np.concatenate([np.arange(33, 65), [63, 57, 2, 40]]).astype(np.int32)
+    offs = np.zeros(len(sizes), np.int64)
+    offs[1:] = np.cumsum(sizes.astype(np.int64) ** 2)[:-1]
+    rng = np.random.default_rng(31)
+    packed = np.zeros(int(offs[-1] + sizes[-1] ** 2), np.float32)
+    for b, n in enumerate(sizes):
+        a = G.random_hpd(rng, 1, int(n), shift=0.5, complex_=False)[0]
+        packed[offs[b]:offs[b] + n * n] = a.astype(np.float32).ravel()
+    bad = {len(sizes) - 4: 62, len(sizes) - 3: 1}     # order 63: pivot 62; order 57: pivot 1
+    for b, piv in bad.items():
+        n = int(sizes[b])
+        m = np.eye(n, dtype=np.float32)
+        m[piv - 1, piv - 1] = -2.0
+        packed[offs[b]:offs[b] + n * n] = m.ravel()
+    out = t.full((packed.size,), 7.0, dtype=t.float32, device="cuda")
+    X, info = api.inverse_varlen(t.from_numpy(packed).cuda(), t.from_numpy(sizes).cuda(),
+                                 t.from_numpy(offs).cuda(), n_max=64, method=method,
+                                 precision=prec, ns_steps=0, fill_lower=fill, out=out,
+                                 return_info=True)
+    info = info.cpu().numpy()
+    x = X.cpu().numpy()
+    xo, io = O.inv_prop_varlen(packed.astype(np.float64), sizes, offs, method)
+    assert np.array_equal(info, io)
+    for b, piv in bad.items():
+        assert info[b] == piv
+        xb = _unpack(x, sizes, offs, b)
+        up = np.triu(np.ones(xb.shape, bool))
+        assert np.all(np.isnan(xb[up]))
+    for b in range(len(sizes)):
+        if b in bad:
+            continue
+        n = int(sizes[b])
+        xb = _unpack(x, sizes, offs, b).astype(np.float64)
+        ref = _unpack(xo, sizes, offs, b)
+        a = _unpack(packed, sizes, offs, b).astype(np.complex128)
+        up = np.triu(np.ones((n, n), bool))
+        if not fill:
+            assert np.all(xb[~up] == 7.0), "order %d: lower triangle written" % n
+            xb = np.where(up, xb, xb.T)
+        else:
+            assert np.array_equal(xb, xb.T)
+        err = np.linalg.norm(xb - ref) / np.linalg.norm(ref)
+        assert err <= TOL_FP32 * O.kappa2(a), "order %d err %.3e" % (n, err)
 
 
 def test_varlen_graph_capture_replays_match_eager():
