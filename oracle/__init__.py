@@ -75,6 +75,7 @@ def _load():
     lib.or_inv_q15.argtypes = [_i32, _vp, _vp, _vp, _vp]
     lib.or_inv_q15.restype = _i32
     lib.or_inv_q15_batched.argtypes = [_i64, _i32, _vp, _vp, _vp, _vp, _vp]
+    lib.or_inv_q15_cmp_batched.argtypes = [_i32, _i64, _i32, _vp, _vp, _vp, _vp, _vp]
     lib.or_inv_nonherm_z.argtypes = [_i32, _vp, _vp]
     lib.or_inv_nonherm_z.restype = _i32
     lib.or_herm_eig_z.argtypes = [_i32, _vp, _i64, _vp]
@@ -225,12 +226,14 @@ def inv_nonherm(d):
     return out, int(info)
 
 
-def inv_q15(q):
+def inv_q15(q, variant="IV.A"):
     """Fixed-point form of the proposed inversion (eqs. 3-4 and Section IV.A in
     Q15 with Q30 sums, integer square root and rounded integer division; the
-    format is this implementation's reading).  q: int16 [batch, n, n, 2]
-    (re, im) standing for q / 2^15.  Returns (x int16 [batch, n, n, 2], xexp,
-    sat, info int32 [batch]) with A^{-1} ~ x 2^xexp."""
+    format is this implementation's reading), or with variant "III.A" / "III.B"
+    the Section III comparison methods in the same format (same factor, same
+    output stage).  q: int16 [batch, n, n, 2] (re, im) standing for q / 2^15.
+    Returns (x int16 [batch, n, n, 2], xexp, sat, info int32 [batch]) with
+    A^{-1} ~ x 2^xexp."""
     q = np.ascontiguousarray(q, dtype=np.int16)
     if q.ndim == 3:
         q = q[None]
@@ -239,7 +242,11 @@ def inv_q15(q):
     xexp = np.zeros(batch, np.int32)
     sat = np.zeros(batch, np.int32)
     info = np.zeros(batch, np.int32)
-    _load().or_inv_q15_batched(batch, n, _p(q), _p(x), _p(xexp), _p(sat), _p(info))
+    if variant == "IV.A":
+        _load().or_inv_q15_batched(batch, n, _p(q), _p(x), _p(xexp), _p(sat), _p(info))
+    else:
+        v = {"III.A": 0, "III.B": 1}[variant]
+        _load().or_inv_q15_cmp_batched(v, batch, n, _p(q), _p(x), _p(xexp), _p(sat), _p(info))
     return x, xexp, sat, info
 
 

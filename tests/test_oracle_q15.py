@@ -150,3 +150,89 @@ def test_q15_y_saturation_and_shift_search():
     assert x[0, 0, 0, 0] == 16384
     assert x[0, n - 1, n - 1, 0] == 1
     assert np.abs(x[0, ..., 0].astype(np.int64)).max() == 16384
+
+
+# ---- the Section III methods in the same fixed-point format ------------------
+VARIANTS = ["III.A", "III.B"]
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_q15_compare_diagonal_powers_of_four_exact(variant):
+    """Diagonal inputs with power-of-four entries: the factor, the forward
+    solutions of III.A, M = R^{-1} of III.B and the inverse are all exact."""
+    n = 7
+    q = np.zeros((1, n, n, 2), np.int16)
+    pw = [13, 11, 9, 7, 5, 13, 3]
+    for i, p in enumerate(pw):
+        q[0, i, i, 0] = 1 << p
+    x, xe, sat, info = O.inv_q15(q, variant)
+    assert info[0] == 0 and sat[0] == 0
+    assert np.array_equal(O.dequant_q15(x, xe)[0], np.diag([2.0 ** (15 - p) for p in pw]))
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_q15_compare_hand_worked_2x2(variant):
+    """A = [[1/4, 1/8], [1/8, 5/16]] (mantissas 8192, 4096, 10240) = R^T R with
+    R = [[1/2, 1/4], [0, 1/2]], exact in Q15 (16384, 8192, 16384; both radicands
+    are 2^28).  min r_ii = 2^14, so F = 2 * 14 - 1 = 27 and G = 14 + 13 - 1 = 26.
+      III.B: M = R^{-1} = [[2, -1], [0, 2]]: w00 = w11 = 2^41 / 2^14 = 2^27,
+             w01 = -(8192 * 2^27) / 16384 = -2^26; X = M M^T with 2G - F = 25:
+             y00 = (2^54 + 2^52) / 2^25 = 5 * 2^27, y01 = -2^53 / 2^25 = -2^28,
+             y11 = 2^54 / 2^25 = 2^29.
+      III.A: column 1: w1 = 2^27, y11 = 2^27 * 2^(27+15-26) / 2^14 = 2^29,
+             y01 = -8192 * 2^29 / 16384 = -2^28; column 0: w0 = 2^27,
+             y00 = (2^27 * 2^16 + 8192 * 2^28) / 16384 = 5 * 2^27.
+    Output: 5 * 2^27 / 2^15 = 20480 fits and 2^14 would not, so the mantissas
+    are (20480, -8192, 16384) with xexp = 15 - 27 = -12: X = [[5, -2], [-2, 4]]."""
+    q = np.zeros((1, 2, 2, 2), np.int16)
+    q[0, :, :, 0] = [[8192, 4096], [4096, 10240]]
+    x, xe, sat, info = O.inv_q15(q, variant)
+    assert info[0] == 0 and sat[0] == 0 and xe[0] == -12
+    assert x[0, :, :, 0].tolist() == [[20480, -8192], [-8192, 16384]]
+    assert (x[0, :, :, 1] == 0).all()
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_q15_compare_within_fixed_point_bound(variant):
+    """Every order 1..16 (random Hermitian) and the MIMO matrices: the same
+    4 kappa n 2^-15 bound against the FP64 inverse of the quantized matrix as
+    the proposed route (reading and derivation in the module docstring)."""
+    rng = np.random.default_rng(13)
+    cases = [G.random_hpd(rng, 20, n, shift=0.3 * n) for n in range(1, 17)]
+    cases += [G.mimo(8, 200, seed=81), G.mimo(16, 200, seed=82)]
+    for a in cases:
+        n = a.shape[-1]
+        q, _ = G.quantize_q15(a)
+        x, xe, sat, info = O.inv_q15(q, variant)
+        assert (info == 0).all()
+        at = _values(q)
+        ref = np.stack([O.inv_prop(m)[0] for m in at])
+        got = O.dequant_q15(x, xe)
+        err = np.linalg.norm(got - ref, axis=(1, 2)) / np.linalg.norm(ref, axis=(1, 2))
+        assert (err <= 4 * kappas(at) * n * 2.0 ** -15).all(), (variant, n)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_q15_compare_hermitian_and_failing_pivot(variant):
+    q, _ = G.quantize_q15(G.mimo(12, 40, seed=6))
+    x, _, _, _ = O.inv_q15(q, variant)
+    xt = np.swapaxes(x, 1, 2)
+    assert np.array_equal(x[..., 0], xt[..., 0]) and np.array_equal(x[..., 1], -xt[..., 1])
+    a = G.random_hpd(np.random.default_rng(9), 1, 6, shift=1.0)[0]
+    a[3, 3] = -a[3, 3]
+    q, _ = G.quantize_q15(a)
+    x, xe, sat, info = O.inv_q15(q, variant)
+    assert info[0] == 4 and (x == 0).all() and xe[0] == 0
+
+
+def test_q15_routes_agree_to_one_unit():
+    """All routes invert the same quantized factor with wide intermediates, so
+    their int16 results agree to one unit of the output mantissa (same
+    exponent) -- an invariant of the method, not of any one implementation."""
+    for n in (4, 8, 16):
+        q, _ = G.quantize_q15(G.mimo(n, 300, seed=90 + n))
+        x0, e0, _, _ = O.inv_q15(q, "IV.A")
+        for v in VARIANTS:
+            x1, e1, _, _ = O.inv_q15(q, v)
+            assert np.array_equal(e0, e1), (n, v)
+            assert np.abs(x1.astype(np.int32) - x0.astype(np.int32)).max() <= 1, (n, v)
