@@ -360,26 +360,39 @@ def q15_workload(torch, api, G, dev, steps):
     """Fixed-point inversion of the 8 x 8 half of the MIMO batch quantized to
     Q15 (524,288 matrices): rate, and the average relative Frobenius error
     against the FP64 inverse of the quantized matrices over a sample (the
-    error measure of the paper's fixed-point comparison)."""
+    error measure of the paper's fixed-point comparison), for the proposed
+    route and the two Section III methods in the same format; the share of
+    sampled matrices where a Section III result equals the proposed one bit
+    for bit."""
     n, count = 8, 1 << 19
     q, _ = G.quantize_q15(G.mimo(n, count))
     Q = torch.from_numpy(q).to(dev)
-    state = {}
-
-    def f():
-        state["r"] = api.inverse_q15(Q)
-
-    ms, _ = _time_loop(torch, [f], steps, 2)
-    x, xe = (t.cpu().numpy() for t in state["r"])
     idx = np.arange(0, count, count // 2048)
     at = (q[idx, ..., 0] + 1j * q[idx, ..., 1]).astype(np.complex128) / 2.0 ** 15
     ref = _ref_inv(at)
-    xs = x[idx].astype(np.float64)
-    got = (xs[..., 0] + 1j * xs[..., 1]) * np.ldexp(1.0, xe[idx])[:, None, None]
-    err = _rel(got, ref)
-    return {"q15_c64_8x8_inv_per_s": count / (ms / 1e3),
-            "q15_c64_8x8_avg_norm_err_vs_lapack": float(err.mean()),
-            "q15_c64_8x8_max_norm_err_vs_lapack": float(err.max())}
+    out = {}
+    first = None
+    for variant, key in (("IV.A", "q15_c64_8x8"), ("III.A", "q15_IIIA_c64_8x8"),
+                         ("III.B", "q15_IIIB_c64_8x8")):
+        state = {}
+
+        def f():
+            state["r"] = api.inverse_q15(Q, variant=variant)
+
+        ms, _ = _time_loop(torch, [f], steps, 2)
+        x, xe = (t.cpu().numpy() for t in state["r"])
+        xs = x[idx].astype(np.float64)
+        got = (xs[..., 0] + 1j * xs[..., 1]) * np.ldexp(1.0, xe[idx])[:, None, None]
+        err = _rel(got, ref)
+        out[key + "_inv_per_s"] = count / (ms / 1e3)
+        out[key + "_avg_norm_err_vs_lapack"] = float(err.mean())
+        out[key + "_max_norm_err_vs_lapack"] = float(err.max())
+        if first is None:
+            first = (x[idx], xe[idx])
+        else:
+            same = np.all(x[idx] == first[0], axis=(1, 2, 3)) & (xe[idx] == first[1])
+            out[key + "_share_equal_to_IVA"] = float(same.mean())
+    return out
 
 
 def compare_workload(torch, api, a8, A8, steps):

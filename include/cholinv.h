@@ -326,6 +326,25 @@ enum { CI_III_A = 0, CI_III_B = 1 };
 int chol_inverse_compare(int dtype, int variant, int method, int64_t batch, int64_t n,
                          const void* a, int64_t stride, void* x, int32_t* info, void* stream);
 
+/*
+ * chol_inverse_q15_compare -- the Section III methods (variant CI_III_A,
+ * equation solving, eq. 15; CI_III_B, triangular operations, eqs. 17-19) in
+ * the fixed-point format of chol_inverse_q15, Cholesky only: the same Q15
+ * factor, the same Y = X 2^F and the same int16 output with one exponent per
+ * matrix; only the route from R to Y differs.  The forward solution of III.A
+ * (one column at a time) and M = R^{-1} of III.B are held as (.) 2^G in int64,
+ * G = floor(log2 min r_ii) + 13 - ceil(ceil(log2 n) / 2), saturating at
+ * +-(2^29 - 1) (counted in sat); every division is the same rounded integer
+ * division.  For side-by-side accuracy comparisons of the three methods on
+ * the same quantized inputs.
+ *   variant      CI_III_A or CI_III_B (argument 1)
+ *   the other arguments as chol_inverse_q15 (numbered from 2)
+ * Results are exact integers: they do not depend on the device or the launch.
+ */
+int chol_inverse_q15_compare(int variant, int64_t batch, int64_t n, const int16_t* a,
+                             int64_t stride, int16_t* x, int32_t* xexp, int32_t* sat,
+                             int32_t* info, void* stream);
+
 /* Which entry point a workspace query is for. */
 enum { CI_FN_FACTOR = 0, CI_FN_INVERSE = 1, CI_FN_BATCHED = 2, CI_FN_NONHERM = 3 };
 

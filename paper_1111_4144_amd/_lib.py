@@ -27,7 +27,7 @@ CI_SMALL_NMAX = 64
 # Every symbol include/cholinv.h declares.
 EXPORTS = ("chol_factor", "ldl_factor", "chol_solve", "chol_inverse", "chol_inverse_batched",
            "chol_inverse_batched_noalloc", "chol_inverse_nonherm", "chol_inverse_q15", "chol_inverse_compare",
-           "chol_inverse_backward", "chol_workspace_size",
+           "chol_inverse_q15_compare", "chol_inverse_backward", "chol_workspace_size",
            "chol_status_string", "chol_version",
            "chol_autotune", "chol_tuned_engine", "chol_tune_set", "chol_autotune_varlen",
            "chol_autotune_clear")
@@ -74,6 +74,7 @@ def lib():
                                        _vp, _sz, _vp, _vp]
     L.chol_inverse_q15.argtypes = [_i64, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp]
     L.chol_inverse_compare.argtypes = [_i32, _i32, _i32, _i64, _i64, _vp, _i64, _vp, _vp, _vp]
+    L.chol_inverse_q15_compare.argtypes = [_i32, _i64, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp]
     L.chol_inverse_backward.argtypes = [_i32, _i64, _i64, _vp, _vp, _vp, _i64, _vp]
     L.chol_workspace_size.argtypes = [_i32, _i32, _i64, _i64, ctypes.POINTER(ci_opts)]
     L.chol_workspace_size.restype = _sz
@@ -91,7 +92,7 @@ def lib():
     L.chol_autotune_clear.restype = None
     for fn in ("chol_factor", "ldl_factor", "chol_solve", "chol_inverse", "chol_inverse_batched",
                "chol_inverse_batched_noalloc", "chol_inverse_nonherm", "chol_inverse_q15", "chol_inverse_compare",
-               "chol_inverse_backward"):
+               "chol_inverse_q15_compare", "chol_inverse_backward"):
         getattr(L, fn).restype = _i32
     _lib = L
     return L

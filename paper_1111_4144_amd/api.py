@@ -273,12 +273,13 @@ def inverse_nonherm(D: torch.Tensor, *, method="chol", precision="plain", ns_ste
     return (X, info.reshape(D.shape[:-2])) if return_info else X
 
 
-def inverse_q15(Q: torch.Tensor, *, return_info=False):
+def inverse_q15(Q: torch.Tensor, *, variant="IV.A", return_info=False):
     """Fixed-point inversion of complex Hermitian matrices given as int16
     mantissas Q[..., n, n, 2] (re, im; value Q / 2^15), n <= 16: Cholesky and
-    the Section IV.A back-substitution in Q15 storage with int64 Q30 sums.
-    Returns (X int16 [..., n, n, 2], xexp int32 [...]) with A^{-1} = X 2^xexp,
-    plus (sat, info) with return_info."""
+    the Section IV.A back-substitution in Q15 storage with int64 Q30 sums
+    (variant "IV.A"), or the Section III methods "III.A" / "III.B" in the same
+    format.  Returns (X int16 [..., n, n, 2], xexp int32 [...]) with
+    A^{-1} = X 2^xexp, plus (sat, info) with return_info."""
     _check_device(Q)
     if Q.dtype != torch.int16 or Q.shape[-1] != 2 or Q.shape[-2] != Q.shape[-3]:
         raise TypeError("Q must be int16 [..., n, n, 2]")
@@ -289,9 +290,15 @@ def inverse_q15(Q: torch.Tensor, *, return_info=False):
     xexp = torch.zeros(B, dtype=torch.int32, device=Q.device)
     sat = torch.zeros(B, dtype=torch.int32, device=Q.device)
     info = torch.zeros(B, dtype=torch.int32, device=Q.device)
-    rc = L.lib().chol_inverse_q15(B, n, _ptr(Q4), n * n, _ptr(X), _ptr(xexp), _ptr(sat),
-                                  _ptr(info), _stream(Q.device))
-    L.check("chol_inverse_q15", rc)
+    if variant == "IV.A":
+        rc = L.lib().chol_inverse_q15(B, n, _ptr(Q4), n * n, _ptr(X), _ptr(xexp), _ptr(sat),
+                                      _ptr(info), _stream(Q.device))
+        L.check("chol_inverse_q15", rc)
+    else:
+        var = {"III.A": L.CI_III_A, "III.B": L.CI_III_B}[variant]
+        rc = L.lib().chol_inverse_q15_compare(var, B, n, _ptr(Q4), n * n, _ptr(X), _ptr(xexp),
+                                              _ptr(sat), _ptr(info), _stream(Q.device))
+        L.check("chol_inverse_q15_compare", rc)
     X = X.reshape(Q.shape)
     lead = Q.shape[:-3]
     if return_info:

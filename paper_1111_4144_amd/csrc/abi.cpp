@@ -214,16 +214,18 @@ int chol_inverse_nonherm(int dtype, int64_t batch, int64_t n, const void* d, int
     return 0;
 }
 
-int chol_inverse_q15(int64_t batch, int64_t n, const int16_t* a, int64_t stride, int16_t* x,
-                     int32_t* xexp, int32_t* sat, int32_t* info, void* stream)
+// Q15 batches for either route; k shifts the argument numbers of the errors
+// (the compare entry point takes the variant first).
+static int q15_run(int variant, int k, int64_t batch, int64_t n, const int16_t* a, int64_t stride,
+                   int16_t* x, int32_t* xexp, int32_t* sat, int32_t* info, void* stream)
 {
-    if (batch < 0) return -1;
-    if (n < 0 || n > CI_Q15_NMAX) return -2;
+    if (batch < 0) return -(1 + k);
+    if (n < 0 || n > CI_Q15_NMAX) return -(2 + k);
     const bool work = batch > 0 && n > 0;
-    if (work && !a) return -3;
-    if (batch > 1 && stride < n * n) return -4;
-    if (work && (!x || x == a)) return -5;
-    if (work && !xexp) return -6;
+    if (work && !a) return -(3 + k);
+    if (batch > 1 && stride < n * n) return -(4 + k);
+    if (work && (!x || x == a)) return -(5 + k);
+    if (work && !xexp) return -(6 + k);
     if (!work) return (batch > 0 && info) ? map_err(ci::fill_i32(info, batch, 0, (hipStream_t)stream)) : 0;
     // one lane per matrix: pieces of 2^30 matrices per launch
     const int64_t st = batch > 1 ? stride : n * n;
@@ -233,10 +235,25 @@ int chol_inverse_q15(int64_t batch, int64_t n, const int16_t* a, int64_t stride,
         const int rc = map_err(ci::launch_inv_q15(a + 2 * b0 * st, st, x + 2 * b0 * st, xexp + b0,
                                                   sat ? sat + b0 : nullptr,
                                                   info ? info + b0 : nullptr, cnt, (int)n,
-                                                  (hipStream_t)stream));
+                                                  (hipStream_t)stream, variant));
         if (rc) return rc;
     }
     return 0;
+}
+
+int chol_inverse_q15(int64_t batch, int64_t n, const int16_t* a, int64_t stride, int16_t* x,
+                     int32_t* xexp, int32_t* sat, int32_t* info, void* stream)
+{
+    return q15_run(0, 0, batch, n, a, stride, x, xexp, sat, info, stream);
+}
+
+int chol_inverse_q15_compare(int variant, int64_t batch, int64_t n, const int16_t* a,
+                             int64_t stride, int16_t* x, int32_t* xexp, int32_t* sat,
+                             int32_t* info, void* stream)
+{
+    if (variant != CI_III_A && variant != CI_III_B) return -1;
+    return q15_run(variant == CI_III_A ? 1 : 2, 1, batch, n, a, stride, x, xexp, sat, info,
+                   stream);
 }
 
 int chol_inverse_compare(int dtype, int variant, int method, int64_t batch, int64_t n,

@@ -10,6 +10,15 @@
 // X = x 2^xexp, the smallest shift that fits.  Every rounding is to nearest
 // with halves away from zero.  Saturations are counted per matrix.
 //
+// The Section III comparison methods run in the same format (variant QV:
+// 1 = III.A, 2 = III.B, Cholesky only): the same factor and output stage;
+// the forward solution b of III.A (one column at a time) and M = R^{-1} of
+// III.B are held as W = (.) 2^G in int64, G = floor(log2 min r_ii) + 13 -
+// ceil(ceil(log2 n) / 2), saturating at +-(2^29 - 1) so that every sum of
+// two-factor products stays below 2^63.  III.B forms X = M M^* in place over
+// M: row i of X, left to right, needs only entries of M right of the one it
+// replaces and rows below it.
+//
 // One lane per matrix.  The integer work is long (int64 products and
 // divisions), so a lane keeps its factor and its Y in LDS, entry-major with
 // the block's 16 lanes interleaved (conflict-free), and the block is small;
@@ -58,15 +67,18 @@ __device__ __forceinline__ int64_t q_sat(int64_t v, int64_t lim, int& sat)
 
 // QN: the order the block's LDS is sized for (8 or 16; n <= QN), so that
 // blocks of small orders take a quarter of the LDS and more of them reside.
-template <int QN>
+// QV: 0 the Section IV.A back-substitution, 1 III.A, 2 III.B.
+template <int QN, int QV>
 __global__ void __launch_bounds__(QL)
 k_inv_q15(const int16_t* __restrict__ a, int64_t stride, int16_t* __restrict__ x,
           int32_t* __restrict__ xexp, int32_t* __restrict__ sat_out, int32_t* __restrict__ info,
           int64_t batch, int n)
 {
     constexpr int QE = QN * (QN + 1) / 2;   // packed upper entries
+    constexpr int QW = (QV == 1) ? QN : 1;  // III.A's forward solution
     __shared__ int32_t Rr[QE * QL], Ri[QE * QL];
     __shared__ int64_t Yr[QE * QL], Yi[QE * QL];
+    __shared__ int64_t Wr[QW * QL], Wi[QW * QL];
     const int l = threadIdx.x;
     const int64_t b = (int64_t)blockIdx.x * QL + l;
     if (b >= batch) return;                 // lanes share no LDS entries
@@ -76,7 +88,9 @@ k_inv_q15(const int16_t* __restrict__ a, int64_t stride, int16_t* __restrict__ x
 #define RI(i, j) Ri[qp<QN>(i, j) * QL + l]
 #define YR(i, j) Yr[qp<QN>(i, j) * QL + l]
 #define YI(i, j) Yi[qp<QN>(i, j) * QL + l]
-    constexpr int64_t QMAX = 32767, YLIM = ((int64_t)1 << 40) - 1;
+#define WR(j) Wr[(j) * QL + l]
+#define WI(j) Wi[(j) * QL + l]
+    constexpr int64_t QMAX = 32767, YLIM = ((int64_t)1 << 40) - 1, WLIM = ((int64_t)1 << 29) - 1;
     int sat = 0, fail = 0;
 
     // eqs. 3-4: R in Q15, sums in Q30
@@ -118,6 +132,69 @@ k_inv_q15(const int16_t* __restrict__ a, int64_t stride, int16_t* __restrict__ x
     while ((1 << lg) < n) ++lg;
     const int F = 2 * bb - lg;
 
+    const int G = bb + 13 - (lg + 1) / 2;
+    if constexpr (QV == 1) {
+        // III.A: columns i = n-1..0; forward R^* b = e_i (rows j >= i), then
+        // backward R x = b (rows j = i..0) with xh_ki = conj(x_ik) for k > i
+        const int64_t up = (int64_t)1 << (F + 15 - G);
+        for (int i = n - 1; i >= 0; --i) {
+            for (int j = i; j < n; ++j) {
+                int64_t sr = (j == i) ? ((int64_t)1 << (G + 15)) : 0, si = 0;
+                for (int k = i; k < j; ++k) {          // conj(r_kj) b_k
+                    const int64_t rr = RR(k, j), ri = RI(k, j), wr = WR(k), wi = WI(k);
+                    sr -= rr * wr + ri * wi;
+                    si -= rr * wi - ri * wr;
+                }
+                const int64_t d = RR(j, j);
+                WR(j) = q_sat(q_div(sr, d), WLIM, sat);
+                WI(j) = q_sat(q_div(si, d), WLIM, sat);
+            }
+            for (int j = i; j >= 0; --j) {
+                int64_t sr = (j == i) ? WR(j) * up : 0, si = (j == i) ? WI(j) * up : 0;
+                for (int k = j + 1; k < n; ++k) {
+                    int64_t hr, hi;
+                    if (k <= i) { hr = YR(k, i); hi = YI(k, i); }
+                    else        { hr = YR(i, k); hi = -YI(i, k); }
+                    const int64_t rr = RR(j, k), ri = RI(j, k);
+                    sr -= rr * hr - ri * hi;
+                    si -= rr * hi + ri * hr;
+                }
+                const int64_t d = RR(j, j);
+                YR(j, i) = q_sat(q_div(sr, d), YLIM, sat);
+                YI(j, i) = (j == i) ? 0 : q_sat(q_div(si, d), YLIM, sat);
+            }
+        }
+    } else if constexpr (QV == 2) {
+        // III.B: M = R^{-1} 2^G in the Y slots, column by column (rows j = i..0)
+        for (int i = 0; i < n; ++i) {
+            YR(i, i) = q_sat(q_div((int64_t)1 << (G + 15), (int64_t)RR(i, i)), WLIM, sat);
+            YI(i, i) = 0;
+            for (int j = i - 1; j >= 0; --j) {
+                int64_t sr = 0, si = 0;
+                for (int k = j + 1; k <= i; ++k) {     // r_jk m_ki
+                    const int64_t rr = RR(j, k), ri = RI(j, k), mr = YR(k, i), mi = YI(k, i);
+                    sr -= rr * mr - ri * mi;
+                    si -= rr * mi + ri * mr;
+                }
+                const int64_t d = RR(j, j);
+                YR(j, i) = q_sat(q_div(sr, d), WLIM, sat);
+                YI(j, i) = q_sat(q_div(si, d), WLIM, sat);
+            }
+        }
+        // X = M M^* upper half, in place: x_ij = sum_{k >= j} m_ik conj(m_jk)
+        const int64_t down = (int64_t)1 << (2 * G - F);
+        for (int i = 0; i < n; ++i)
+            for (int j = i; j < n; ++j) {
+                int64_t sr = 0, si = 0;
+                for (int k = j; k < n; ++k) {
+                    const int64_t ar = YR(i, k), ai = YI(i, k), br = YR(j, k), bi = YI(j, k);
+                    sr += ar * br + ai * bi;
+                    si += ai * br - ar * bi;
+                }
+                YR(i, j) = q_sat(q_div(sr, down), YLIM, sat);
+                YI(i, j) = (j == i) ? 0 : q_sat(q_div(si, down), YLIM, sat);
+            }
+    } else {
     // Section IV.A: rows bottom-up, each row's diagonal last
     for (int i = n - 1; i >= 0; --i) {
         const int64_t d = RR(i, i);
@@ -135,6 +212,7 @@ k_inv_q15(const int16_t* __restrict__ a, int64_t stride, int16_t* __restrict__ x
             YR(i, j) = q_sat(q_div(sr, d), YLIM, sat);
             YI(i, j) = (j == i) ? 0 : q_sat(q_div(si, d), YLIM, sat);
         }
+    }
     }
 
     int64_t m = 0;
@@ -161,21 +239,37 @@ k_inv_q15(const int16_t* __restrict__ a, int64_t stride, int16_t* __restrict__ x
 #undef RI
 #undef YR
 #undef YI
+#undef WR
+#undef WI
 }
 
 }  // namespace
 
+template <int QV>
+static void launch_q15_variant(const int16_t* a, int64_t stride, int16_t* x, int32_t* xexp,
+                               int32_t* sat, int32_t* info, int64_t batch, int n, hipStream_t s)
+{
+    const dim3 grid((unsigned)((batch + QL - 1) / QL)), block(QL);
+    if (n <= 8)
+        hipLaunchKernelGGL((k_inv_q15<8, QV>), grid, block, 0, s, a, stride, x, xexp, sat, info,
+                           batch, n);
+    else
+        hipLaunchKernelGGL((k_inv_q15<16, QV>), grid, block, 0, s, a, stride, x, xexp, sat, info,
+                           batch, n);
+}
+
 hipError_t launch_inv_q15(const int16_t* a, int64_t stride, int16_t* x, int32_t* xexp,
-                          int32_t* sat, int32_t* info, int64_t batch, int n, hipStream_t s)
+                          int32_t* sat, int32_t* info, int64_t batch, int n, hipStream_t s,
+                          int variant)
 {
     if (batch <= 0 || n <= 0) return hipSuccess;
     if (n > QN_MAX) return hipErrorNotSupported;
-    const dim3 grid((unsigned)((batch + QL - 1) / QL)), block(QL);
-    if (n <= 8)
-        hipLaunchKernelGGL(k_inv_q15<8>, grid, block, 0, s, a, stride, x, xexp, sat, info, batch, n);
-    else
-        hipLaunchKernelGGL(k_inv_q15<16>, grid, block, 0, s, a, stride, x, xexp, sat, info, batch,
-                           n);
+    switch (variant) {
+    case 0: launch_q15_variant<0>(a, stride, x, xexp, sat, info, batch, n, s); break;
+    case 1: launch_q15_variant<1>(a, stride, x, xexp, sat, info, batch, n, s); break;
+    case 2: launch_q15_variant<2>(a, stride, x, xexp, sat, info, batch, n, s); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -13,20 +13,21 @@ from tests.helpers import torch_cuda
 pytestmark = pytest.mark.gpu
 
 
-def _gpu(q):
+def _gpu(q, variant="IV.A"):
     t = torch_cuda()
     from paper_1111_4144_amd import api
     x, xe, sat, info = api.inverse_q15(t.from_numpy(np.ascontiguousarray(q)).cuda(),
-                                       return_info=True)
+                                       variant=variant, return_info=True)
     t.cuda.synchronize()
     return x.cpu().numpy(), xe.cpu().numpy(), sat.cpu().numpy(), info.cpu().numpy()
 
 
-def _same(q):
-    got = _gpu(q)
-    want = O.inv_q15(q)
+def _same(q, variant="IV.A"):
+    got = _gpu(q, variant)
+    want = O.inv_q15(q, variant)
     for name, g, w in zip(("x", "xexp", "sat", "info"), got, want):
-        assert np.array_equal(g, w), "%s differs at %d entries" % (name, int((g != w).sum()))
+        assert np.array_equal(g, w), "%s %s differs at %d entries" % (variant, name,
+                                                                     int((g != w).sum()))
     return want
 
 
@@ -79,3 +80,47 @@ def test_q15_hand_worked_cases():
             q10[0, i, j, 0] = 2048 * (i + 1) if i == j else 2048 * (min(i, j) - 1)
     x, xe, sat, info = _same(q10)
     assert sat[0] >= 1 and xe[0] == 4 and x[0, 0, 0, 0] == 16384
+
+
+# ---- the Section III methods in the same format --------------------------------
+@pytest.mark.parametrize("variant", ["III.A", "III.B"])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 9, 12, 16])
+def test_q15_compare_bit_exact(n, variant):
+    q, _ = G.quantize_q15(G.mimo(n, 37, seed=301 + n))
+    x, xe, sat, info = _same(q, variant)
+    assert (info == 0).all()
+
+
+@pytest.mark.parametrize("variant", ["III.A", "III.B"])
+def test_q15_compare_edge_cases(variant):
+    """Failing pivots, a saturating factor, and the oracle's hand-worked exact
+    2 x 2 case (X = [[5, -2], [-2, 4]]), bit for bit."""
+    rng = np.random.default_rng(14)
+    a = G.random_hpd(rng, 40, 9, shift=1.0)
+    a[5, 4, 4] = -a[5, 4, 4]
+    a[17, 0, 0] = -1.0
+    q, _ = G.quantize_q15(a)
+    s2 = np.zeros((3, 9, 9, 2), np.int16)
+    for m in range(3):
+        s2[m, :, :, 0] = np.eye(9, dtype=np.int16) * 16384
+        s2[m, 0:2, 0:2, 0] = [[32766, 32766], [32766, 32767]]
+    x, xe, sat, info = _same(np.concatenate([q, s2]), variant)
+    assert info[5] == 5 and info[17] == 1 and (sat[-3:] >= 1).all()
+    q2 = np.zeros((1, 2, 2, 2), np.int16)
+    q2[0, :, :, 0] = [[8192, 4096], [4096, 10240]]
+    x, xe, sat, info = _same(q2, variant)
+    assert x[0, :, :, 0].tolist() == [[20480, -8192], [-8192, 16384]] and xe[0] == -12
+
+
+def test_q15_compare_rejects_bad_variant():
+    t = torch_cuda()
+    from paper_1111_4144_amd import _lib as L
+    q = t.zeros((4, 4, 4, 2), dtype=t.int16, device="cuda")
+    x = t.empty_like(q)
+    e = t.empty(4, dtype=t.int32, device="cuda")
+    rc = L.lib().chol_inverse_q15_compare(7, 4, 4, q.data_ptr(), 16, x.data_ptr(), e.data_ptr(),
+                                          None, None, None)
+    assert rc == -1
+    rc = L.lib().chol_inverse_q15_compare(L.CI_III_B, 4, 17, q.data_ptr(), 16, x.data_ptr(),
+                                          e.data_ptr(), None, None, None)
+    assert rc == -3
