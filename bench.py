@@ -397,14 +397,18 @@ def q15_workload(torch, api, G, dev, steps):
 
 def compare_workload(torch, api, a8, A8, steps):
     """Side by side on the 8 x 8 half of the MIMO batch (524,288 complex64,
-    plain FP32 arithmetic): the Section III.A and III.B comparison kernels and
-    the proposed method's plain-FP32 engine; rates and sampled errors against
-    FP64 library inverses (the comparison kernels are straightforward one-lane
-    implementations, so their rates are context, not tuned baselines)."""
+    plain FP32 arithmetic): the Section III.A and III.B comparison kernels,
+    the Section IV route in the same framework (same factor code, LDS layout
+    and arithmetic: the like-for-like reference, "IVsame"), and the proposed
+    method's tuned plain-FP32 engine; rates and sampled errors against FP64
+    library inverses.  The three framework kernels differ only by their route
+    from R to X, so their time ratios read against the operation counts
+    (N = 8: 252, 420 and 372 complex multiplies)."""
     out = {}
     idx = np.arange(0, a8.shape[0], a8.shape[0] // 1024)
     ref = _ref_inv(a8[idx])
     cases = [("IV", lambda: api.inverse(A8)),
+             ("IVsame", lambda: api.inverse_compare(A8, variant="IV")),
              ("IIIA", lambda: api.inverse_compare(A8, variant="III.A")),
              ("IIIB", lambda: api.inverse_compare(A8, variant="III.B"))]
     for name, fn in cases:

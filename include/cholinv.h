@@ -313,6 +313,10 @@ int chol_inverse_q15(int64_t batch, int64_t n, const int16_t* a, int64_t stride,
  *             CI_METHOD_CHOL) or LDL (CI_METHOD_LDL) factorisation
  *   CI_III_B  Section III.B, triangular operations: M = R^{-1} (eq. 18), then
  *             the upper half of X = M M^* (eq. 19); Cholesky only
+ *   CI_IV_SAME  the proposed Section IV back-substitution (Cholesky or LDL)
+ *             in this same framework (same factor code, LDS layout and
+ *             arithmetic), the reference point the other two are compared
+ *             with: the three differ only by their route from R to X
  *   a, stride  device input, matrix b at a + b*stride (stride >= n*n;
  *              ignored when batch == 1), leading dimension n; upper triangle
  *              read
@@ -322,7 +326,7 @@ int chol_inverse_q15(int64_t batch, int64_t n, const int16_t* a, int64_t stride,
  *              a finite positive number); the X of a failed matrix is NaN
  */
 #define CI_COMPARE_NMAX 16
-enum { CI_III_A = 0, CI_III_B = 1 };
+enum { CI_III_A = 0, CI_III_B = 1, CI_IV_SAME = 2 };
 int chol_inverse_compare(int dtype, int variant, int method, int64_t batch, int64_t n,
                          const void* a, int64_t stride, void* x, int32_t* info, void* stream);
 

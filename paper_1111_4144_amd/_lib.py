@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libcholinv.so")
 
 CI_F32, CI_F64, CI_C64, CI_C128 = 0, 1, 2, 3
 CI_METHOD_CHOL, CI_METHOD_LDL = 0, 1
-CI_III_A, CI_III_B = 0, 1
+CI_III_A, CI_III_B, CI_IV_SAME = 0, 1, 2
 CI_PLAIN, CI_MIXED = 0, 1
 CI_FN_FACTOR, CI_FN_INVERSE, CI_FN_BATCHED, CI_FN_NONHERM = 0, 1, 2, 3
 CI_ERR_UNSUPPORTED = -2000

@@ -309,9 +309,11 @@ def inverse_q15(Q: torch.Tensor, *, variant="IV.A", return_info=False):
 def inverse_compare(A: torch.Tensor, *, variant="III.A", method="chol", return_info=False):
     """The comparison methods of Section III on the GPU (orders <= 16, element
     type arithmetic): "III.A" equation solving (eq. 15; Cholesky or LDL) or
-    "III.B" triangular operations (eqs. 17-19; Cholesky).  X in full."""
+    "III.B" triangular operations (eqs. 17-19; Cholesky); "IV" is the
+    proposed Section IV route in the same framework (same factor code and
+    arithmetic), the like-for-like reference.  X in full."""
     _check_device(A)
-    var = {"III.A": L.CI_III_A, "III.B": L.CI_III_B}[variant]
+    var = {"III.A": L.CI_III_A, "III.B": L.CI_III_B, "IV": L.CI_IV_SAME}[variant]
     meth = {"chol": L.CI_METHOD_CHOL, "ldl": L.CI_METHOD_LDL}[method]
     n = A.shape[-1]
     A3 = A.reshape(-1, n, n).contiguous()

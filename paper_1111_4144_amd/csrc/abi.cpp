@@ -260,8 +260,8 @@ int chol_inverse_compare(int dtype, int variant, int method, int64_t batch, int6
                          const void* a, int64_t stride, void* x, int32_t* info, void* stream)
 {
     if (!valid_dtype(dtype)) return -1;
-    if (variant != CI_III_A && variant != CI_III_B) return -2;
-    if (method != CI_METHOD_CHOL && (method != CI_METHOD_LDL || variant != CI_III_A)) return -3;
+    if (variant != CI_III_A && variant != CI_III_B && variant != CI_IV_SAME) return -2;
+    if (method != CI_METHOD_CHOL && (method != CI_METHOD_LDL || variant == CI_III_B)) return -3;
     if (batch < 0) return -4;
     if (n < 0 || n > CI_COMPARE_NMAX) return -5;
     const bool work = batch > 0 && n > 0;
@@ -270,7 +270,8 @@ int chol_inverse_compare(int dtype, int variant, int method, int64_t batch, int6
     if (work && (!x || x == a)) return -8;
     hipStream_t s = (hipStream_t)stream;
     if (!work) return (batch > 0 && info) ? map_err(ci::fill_i32(info, batch, 0, s)) : 0;
-    const int k = variant == CI_III_B ? 2 : (method == CI_METHOD_LDL ? 1 : 0);
+    const int ldl = method == CI_METHOD_LDL ? 1 : 0;
+    const int k = variant == CI_III_B ? 2 : (variant == CI_IV_SAME ? 3 + ldl : ldl);
     const int64_t st = batch > 1 ? stride : n * n;
     const size_t es = elem_size(dtype);
     constexpr int64_t chunk = (int64_t)1 << 30;          // one lane per matrix

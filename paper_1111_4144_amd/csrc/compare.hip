@@ -5,7 +5,11 @@
 //     column with the already finished columns supplying the rest by the
 //     mirror (Cholesky or LDL factor);
 //   Section III.B, triangular operations: M = R^{-1} column by column from
-//     R m_i = e_i (eq. 18), then the upper half of X = M M^* (eq. 19).
+//     R m_i = e_i (eq. 18), then the upper half of X = M M^* (eq. 19);
+// and, as the reference point of the comparison, the proposed Section IV
+// back-substitution in this same framework (same factor code, same LDS
+// layout, same reciprocal-then-multiply arithmetic), so that the three
+// methods' errors and times differ only by their route from R to X.
 // Orders up to 16, one lane per matrix, arithmetic in the element type.  The
 // factor and X live in LDS (entry-major, the block's 8 lanes interleaved);
 // III.B keeps M in X's place and overwrites it row by row in increasing
@@ -29,7 +33,8 @@ __device__ __forceinline__ int cp(int i, int j) { return i * CN - (i * (i - 1)) 
 
 template <class V> CI_D V cmul(V a, V b) { V acc = mk<V>(typename vt<V>::real(0)); madd(acc, a, b); return acc; }
 
-// VARIANT 0: III.A with Cholesky, 1: III.A with LDL, 2: III.B (Cholesky)
+// VARIANT 0: III.A with Cholesky, 1: III.A with LDL, 2: III.B (Cholesky),
+// 3: Section IV with Cholesky, 4: Section IV with LDL
 template <class V, int VARIANT>
 __global__ void __launch_bounds__(CL)
 k_compare(const V* __restrict__ a, int64_t sa, V* __restrict__ x, int64_t sx,
@@ -49,7 +54,7 @@ k_compare(const V* __restrict__ a, int64_t sa, V* __restrict__ x, int64_t sx,
 #define FS(k) Fs[(k) * CL + l]
 #define DS(k) Ds[(k) * CL + l]
 #define XS(i, j) Xs[((i) * CN + (j)) * CL + l]
-    constexpr bool LDL = VARIANT == 1;
+    constexpr bool LDL = VARIANT == 1 || VARIANT == 4;
     int fail = 0;
     // ---- factor: eqs. 3-4, or 10-11 for LDL ----
     for (int i = 0; i < n && !fail; ++i) {
@@ -99,6 +104,23 @@ k_compare(const V* __restrict__ a, int64_t sa, V* __restrict__ x, int64_t sx,
                 XS(j, i) = v;
             }
         }
+    } else if constexpr (VARIANT >= 3) {
+        // ---- Section IV: rows from the bottom, each row's diagonal last:
+        // x_ij = (delta_ij s_i - sum_{k>i} r_ik xh_kj) s_i (LDL: without the
+        // second s_i), s_i = 1/r_ii or 1/d_i ----
+        for (int i = n - 1; i >= 0; --i) {
+            const R si = R(1) / DS(i);
+            for (int j = n - 1; j >= i; --j) {
+                V acc = mk<V>(j == i ? si : R(0));
+                for (int k = i + 1; k < n; ++k) {
+                    const V xh = (k <= j) ? XS(k, j) : cj(XS(j, k));
+                    acc = add(acc, neg(cmul(RS(i, k), xh)));
+                }
+                V v = LDL ? acc : scal(acc, si);
+                if (j == i) v = realpart_only(v);
+                XS(i, j) = v;
+            }
+        }
     } else {
         // ---- III.B: M = R^{-1} (eq. 18) into X's upper triangle ----
         for (int i = 0; i < n; ++i)
@@ -133,8 +155,12 @@ hipError_t compare_t(int variant, const void* a, int64_t sa, void* x, int64_t sx
         hipLaunchKernelGGL((k_compare<V, 0>), grid, block, 0, s, (const V*)a, sa, (V*)x, sx, info, batch, n);
     else if (variant == 1)
         hipLaunchKernelGGL((k_compare<V, 1>), grid, block, 0, s, (const V*)a, sa, (V*)x, sx, info, batch, n);
-    else
+    else if (variant == 2)
         hipLaunchKernelGGL((k_compare<V, 2>), grid, block, 0, s, (const V*)a, sa, (V*)x, sx, info, batch, n);
+    else if (variant == 3)
+        hipLaunchKernelGGL((k_compare<V, 3>), grid, block, 0, s, (const V*)a, sa, (V*)x, sx, info, batch, n);
+    else
+        hipLaunchKernelGGL((k_compare<V, 4>), grid, block, 0, s, (const V*)a, sa, (V*)x, sx, info, batch, n);
     return hipGetLastError();
 }
 
@@ -144,7 +170,7 @@ hipError_t launch_compare(int dtype, int variant, const void* a, int64_t sa, voi
                           int32_t* info, int64_t batch, int n, hipStream_t s)
 {
     if (batch <= 0 || n <= 0) return hipSuccess;
-    if (n > CN || variant < 0 || variant > 2) return hipErrorNotSupported;
+    if (n > CN || variant < 0 || variant > 4) return hipErrorNotSupported;
     switch (dtype) {
     case DT_F32: return compare_t<float>(variant, a, sa, x, sx, info, batch, n, s);
     case DT_F64: return compare_t<double>(variant, a, sa, x, sx, info, batch, n, s);

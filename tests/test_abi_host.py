@@ -92,7 +92,11 @@ def test_argument_validation_codes():
     assert lib.chol_inverse_q15(2, 4, p, 16, p, q, None, None, None) == -5
     assert lib.chol_inverse_q15(2, 4, p, 16, q, None, None, None, None) == -6
     # comparison methods: unknown variant, LDL with III.B, order beyond 16
-    assert lib.chol_inverse_compare(2, 2, 0, 2, 4, p, 16, q, None, None) == -2
+    assert lib.chol_inverse_compare(2, 3, 0, 2, 4, p, 16, q, None, None) == -2
+    assert lib.chol_inverse_compare(2, L.CI_IV_SAME, 2, 2, 4, p, 16, q, None, None) == -3
+    # the fixed-point comparison: unknown variant, order beyond 16
+    assert lib.chol_inverse_q15_compare(L.CI_IV_SAME, 2, 4, p, 16, q, q, None, None, None) == -1
+    assert lib.chol_inverse_q15_compare(L.CI_III_B, 2, 17, p, 17 * 17, q, q, None, None, None) == -3
     assert lib.chol_inverse_compare(2, L.CI_III_B, 1, 2, 4, p, 16, q, None, None) == -3
     assert lib.chol_inverse_compare(2, L.CI_III_A, 0, 2, 17, p, 17 * 17, q, None, None) == -5
     # empty work is a no-op

@@ -1,6 +1,7 @@
 """GPU parity of the Section III comparison methods (III.A equation solving,
-eq. 15, with Cholesky or LDL; III.B triangular operations, eqs. 17-19)
-against the oracle's implementations of the same methods: relative Frobenius
+eq. 15, with Cholesky or LDL; III.B triangular operations, eqs. 17-19) and of
+the Section IV route in the same framework, against the oracle's
+implementations of the same methods: relative Frobenius
 error per matrix <= 1e-12 kappa (FP64 types) or 2e-6 kappa (FP32 types);
 failures give the oracle's pivot index and NaN."""
 import numpy as np
@@ -25,7 +26,8 @@ def _run(a, variant, method):
     return x.cpu().numpy(), info.cpu().numpy()
 
 
-@pytest.mark.parametrize("variant,method", [("III.A", "chol"), ("III.A", "ldl"), ("III.B", "chol")])
+@pytest.mark.parametrize("variant,method", [("III.A", "chol"), ("III.A", "ldl"), ("III.B", "chol"),
+                                            ("IV", "chol"), ("IV", "ldl")])
 @pytest.mark.parametrize("dt", ["f32", "f64", "c64", "c128"])
 @pytest.mark.parametrize("n", [1, 3, 8, 13, 16])
 def test_compare_vs_oracle(n, dt, variant, method):
@@ -34,6 +36,8 @@ def test_compare_vs_oracle(n, dt, variant, method):
     aw = a.astype(np.complex128 if dt.startswith("c") else np.float64)
     if variant == "III.A":
         ref = np.stack([O.inv_eqsolve(m, method)[0] for m in aw])
+    elif variant == "IV":
+        ref = np.stack([O.inv_prop(m, method)[0] for m in aw])
     else:
         ref = np.stack([O.inv_tri(m)[0] for m in aw])
     x, info = _run(a, variant, method)
@@ -46,7 +50,8 @@ def test_compare_failure_reports_pivot():
     rng = np.random.default_rng(2)
     a = G.random_hpd(rng, 20, 9, shift=1.0, complex_=True)
     a[6, 5, 5] = -abs(a[6, 5, 5])
-    for variant, method in [("III.A", "chol"), ("III.A", "ldl"), ("III.B", "chol")]:
+    for variant, method in [("III.A", "chol"), ("III.A", "ldl"), ("III.B", "chol"),
+                            ("IV", "chol"), ("IV", "ldl")]:
         x, info = _run(a, variant, method)
         want = O.chol(a[6])[1]
         assert want == 6 and info[6] == want
