@@ -31,7 +31,7 @@
  * The return value reports argument and launch errors at once:
  *     0                    success (work queued)
  *    -k  (1 <= k < 100)    argument number k (1-based) is invalid
- *    CI_ERR_UNSUPPORTED    valid arguments but a combination this build lacks
+ *    CI_ERR_UNSUPPORTED    valid arguments but a combination the library lacks
  *    CI_ERR_WORKSPACE      work_bytes smaller than chol_workspace_size()
  *    CI_ERR_NOALLOC_LIMIT  uneven batch above CI_NOALLOC_MAX_BATCH
  *                          (allocation-free entry point only)
