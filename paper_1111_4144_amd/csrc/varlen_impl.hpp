@@ -19,6 +19,7 @@
 #pragma once
 
 #include "group_impl.hpp"
+#include "leaf_impl.hpp"
 #include "tpm_impl.hpp"
 #include "wpm_impl.hpp"
 
@@ -217,6 +218,113 @@ k_varlen_big(const V* __restrict__ a, V* x, const int64_t* __restrict__ offs,
     }
 }
 
+// The last bucket for real float matrices by Cholesky without refinement:
+// one matrix per four-wave workgroup, padded to order 64 with the identity;
+// R and Y = R^{-1} by the sub-blocked routine of leaf_impl.hpp (the updates
+// on the matrix cores, five barriers per 16 columns instead of three per
+// row), then X = Y Y^T (the Section III.B product, whose leading operation
+// count equals Section IV's once R^{-1} skips its zero blocks) as upper 16 x 16
+// MFMA tiles, staged in LDS over R for row-major stores.
+constexpr int VL_LEAF_NB = 64;
+template <int MIXED>
+constexpr size_t vl_leaf_smem()
+{
+    return (size_t)2 * VL_LEAF_NB * lf_ld<float, VL_LEAF_NB>() * sizeof(float) +
+           VL_LEAF_NB * sizeof(double);
+}
+
+template <int MIXED>
+__global__ void __launch_bounds__(LF_THREADS)
+k_varlen_leaf(const float* __restrict__ a, float* x, const int64_t* __restrict__ offs,
+              const int32_t* __restrict__ sorted, VarlenPlan* plan, int fill,
+              int32_t* __restrict__ info)
+{
+    constexpr int NB = VL_LEAF_NB, LD = lf_ld<float, NB>();
+    constexpr int NT = (NB / 16) * (NB / 16 + 1) / 2;       // upper 16 x 16 tiles of X
+    constexpr int TPW = (NT + 3) / 4;                        // tiles per wave
+    using Acc = typename mfma_acc<float>::type;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float* Rm = reinterpret_cast<float*>(smem_raw);          // R, then X (row major, upper)
+    float* Ym = Rm + NB * LD;                                // R^{-1}
+    double* dl = reinterpret_cast<double*>(Ym + NB * LD);    // FP64 pivot accumulators
+    __shared__ int s_tile, s_fail;
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    const int g = lane / 16, cc = lane % 16;
+    for (;;) {
+        if (tid == 0) s_tile = atomicAdd(&plan->next_big, 1);
+        __syncthreads();
+        const int t = s_tile;
+        __syncthreads();
+        if (t >= plan->nbig) break;
+        int n = 64;
+        while (n > plan->big_from && t >= plan->tile_end[n]) --n;
+        const int b = sorted[plan->item_start[n] + (t - plan->tile_start[n])];
+        const float* ab = a + offs[b];
+        float* xb = x + offs[b];
+        // upper triangle of A (identity beyond n); Y starts at zero
+        {
+            constexpr int PER = NB * NB / LF_THREADS;
+            float v[PER];
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int e = tid + LF_THREADS * u, k = e / NB, j = e % NB;
+                v[u] = (k == j) ? 1.f : 0.f;
+                if (j < n && k < n && k <= j) v[u] = ab[k * n + j];
+            }
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int e = tid + LF_THREADS * u, k = e / NB, j = e % NB;
+                Rm[k * LD + j] = (k <= j) ? v[u] : 0.f;
+                Ym[k * LD + j] = 0.f;
+            }
+        }
+        if (MIXED)
+            for (int j = tid; j < NB; j += LF_THREADS) dl[j] = (j < n) ? (double)ab[j * n + j] : 1.0;
+        __syncthreads();
+        const int f = lf_factor_inverse<float, NB, MIXED>(Rm, Ym, dl, n);
+        if (tid == 0) s_fail = f;
+        // X = Y Y^T: x_ij = sum_{k >= j} y_ik y_jk (i <= j), tile (tr, tc) from k = 16 tc
+        Acc xa[TPW];
+#pragma unroll
+        for (int u = 0; u < TPW; ++u) {
+            xa[u] = Acc{0, 0, 0, 0};
+            const int q = wave + 4 * u;
+            if (q < NT) {
+                int tr = 0, rem = q;
+                while (rem >= NB / 16 - tr) { rem -= NB / 16 - tr; ++tr; }
+                const int tc = tr + rem;
+                lf_tile<float>(xa[u], NB - 16 * tc, g, cc,
+                               [&](int r, int k) { return Ym[(16 * tr + r) * LD + 16 * tc + k]; },
+                               [&](int k, int c) { return Ym[(16 * tc + c) * LD + 16 * tc + k]; });
+            }
+        }
+        __syncthreads();                                     // R is no longer read
+#pragma unroll
+        for (int u = 0; u < TPW; ++u) {
+            const int q = wave + 4 * u;
+            if (q < NT) {
+                int tr = 0, rem = q;
+                while (rem >= NB / 16 - tr) { rem -= NB / 16 - tr; ++tr; }
+                const int tc = tr + rem;
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    Rm[(16 * tr + mfma_acc<float>::row(g, v)) * LD + 16 * tc + cc] = xa[u][v];
+            }
+        }
+        __syncthreads();
+        const int fl = s_fail;
+        for (int e = tid; e < n * n; e += LF_THREADS) {
+            const int i = e / n, j = e % n;
+            if (j >= i || fill) {
+                const float v = (j >= i) ? Rm[i * LD + j] : Rm[j * LD + i];
+                xb[e] = fl ? __builtin_nanf("") : v;
+            }
+        }
+        if (tid == 0 && info) info[b] = fl;
+        __syncthreads();                                     // LDS free for the next matrix
+    }
+}
+
 constexpr size_t varlen_plan_bytes() { return (sizeof(VarlenPlan) + 255) / 256 * 256; }
 
 template <class V, int METHOD, int MIXED>
@@ -257,9 +365,29 @@ static hipError_t varlen_run(int64_t batch, const int32_t* n_dev, const int64_t*
         return (int64_t)device_cus() * per_cu;
     };
     if (n_max >= big_from) {
-        hipLaunchKernelGGL(kbig, dim3((unsigned)grid_of((const void*)kbig, 64 * VL_BIG_TPC, s64)),
-                           dim3(64 * VL_BIG_TPC), s64, s, (const V*)a, (V*)x, off_dev, sorted, plan,
-                           ns_steps, fill, info);
+        bool leaf = false;       // real float, Cholesky, no refinement: the MFMA route
+        if constexpr (std::is_same<V, float>::value && METHOD == 0) {
+            leaf = !MIXED || ns_steps == 0;
+            if (leaf) {
+                auto kl = k_varlen_leaf<MIXED>;
+                constexpr size_t sl = vl_leaf_smem<MIXED>();
+                static bool lattr = false;
+                if (!lattr) {
+                    e = hipFuncSetAttribute((const void*)kl,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sl);
+                    if (e != hipSuccess) return e;
+                    lattr = true;
+                }
+                hipLaunchKernelGGL(kl, dim3((unsigned)grid_of((const void*)kl, LF_THREADS, sl)),
+                                   dim3(LF_THREADS), sl, s, (const float*)a, (float*)x, off_dev,
+                                   sorted, plan, fill, info);
+            }
+        }
+        if (!leaf)
+            hipLaunchKernelGGL(kbig,
+                               dim3((unsigned)grid_of((const void*)kbig, 64 * VL_BIG_TPC, s64)),
+                               dim3(64 * VL_BIG_TPC), s64, s, (const V*)a, (V*)x, off_dev, sorted,
+                               plan, ns_steps, fill, info);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
