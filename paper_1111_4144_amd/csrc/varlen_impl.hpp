@@ -9,13 +9,16 @@
 // Tiles: an order n <= 8 tile is up to 64 matrices (one lane each, registers);
 // 9..16 up to 4 matrices (16-lane groups padded to 16 with the identity,
 // which leaves the n x n block exact); 17..32 up to 2 (LDS-resident, one lane
-// per column) and 33..64 one matrix (LDS-resident, four lanes per column,
-// four waves).  The edge of the last bucket (33) can move down to 25 or 17
-// (a tuned choice): those orders then take whole four-wave blocks.  Two
-// persistent kernels, one per block shape, take tiles from their own atomic
-// counters until none are left (every wave reaches that exit): first the
-// last bucket, then the rest, largest orders first within each.  Results do
-// not depend on which wave takes which tile.
+// per column) and 33..64 one matrix: one wave on the matrix cores for real
+// float by Cholesky without refinement, else four waves with four lanes per
+// column (LDS-resident).  The edge of the last bucket (33) can move down to 25
+// or 17 (a tuned choice): those orders then go to the last bucket's kernel.
+// Two persistent kernels, one per block shape, take tiles from their own
+// atomic counters until none are left (every wave reaches that exit): first
+// the last bucket, then the rest, largest orders first within each.  The
+// order of a tile comes from the plan's per-order table held one order per
+// lane (a ballot, no dependent loads).  Results do not depend on which wave
+// takes which tile.
 #pragma once
 
 #include "group_impl.hpp"
@@ -39,6 +42,17 @@ struct VarlenPlan {
 };
 
 CI_D int vl_tile_size(int n) { return n <= 8 ? 64 : n <= 16 ? 4 : n <= 32 ? 2 : 1; }
+
+// Order of tile t.  Tiles run largest order first, so the orders whose tile
+// range ends at or before t form the top of (lo, 64]; lane l of the wave holds
+// te = tile_end of order l + 1, and one ballot counts them (no chain of
+// dependent loads).  Every lane of the wave calls this together.
+CI_D int vl_order_of(int t, int te, int lo)
+{
+    const int l = (int)(threadIdx.x % 64);
+    return 64 - __popcll(__ballot(l + 1 > lo && t >= te));
+}
+CI_D int vl_lane_of(int v, int n) { return __builtin_amdgcn_readlane(v, n - 1); }
 
 __global__ void k_vl_init(VarlenPlan* plan)
 {
@@ -137,18 +151,21 @@ k_varlen(const V* __restrict__ a, V* x, const int64_t* __restrict__ offs,
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int s_tile;
     const int lane = threadIdx.x;
+    // the plan's per-order table, order lane + 1 in lane `lane`
+    const int te = plan->tile_end[lane + 1], ts = plan->tile_start[lane + 1];
+    const int is = plan->item_start[lane + 1], ct = plan->count[lane + 1];
+    const int ntiles = plan->ntiles;
     for (;;) {
         if (lane == 0) s_tile = atomicAdd(&plan->next, 1);
         __syncthreads();
         const int t = s_tile;
         __syncthreads();
-        if (t >= plan->ntiles) break;
-        int n = 64;
-        while (n > 1 && t >= plan->tile_end[n]) --n;
+        if (t >= ntiles) break;
+        const int n = vl_order_of(t, te, 1);
         const int per = vl_tile_size(n);
-        const int k = t - plan->tile_start[n];
-        const int first = plan->item_start[n] + k * per;
-        const int cnt = min(per, plan->count[n] - k * per);
+        const int k = t - vl_lane_of(ts, n);
+        const int first = vl_lane_of(is, n) + k * per;
+        const int cnt = min(per, vl_lane_of(ct, n) - k * per);
         if (n <= 8) {
             if (lane < cnt) {
                 const int b = sorted[first + lane];
@@ -200,16 +217,18 @@ k_varlen_big(const V* __restrict__ a, V* x, const int64_t* __restrict__ offs,
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int s_tile;
-    const int j = threadIdx.x / VL_BIG_TPC, h = threadIdx.x % VL_BIG_TPC;
+    const int j = threadIdx.x / VL_BIG_TPC, h = threadIdx.x % VL_BIG_TPC, l = threadIdx.x % 64;
+    const int te = plan->tile_end[l + 1], ts = plan->tile_start[l + 1];
+    const int is = plan->item_start[l + 1];
+    const int nbig = plan->nbig, lo = plan->big_from;
     for (;;) {
         if (threadIdx.x == 0) s_tile = atomicAdd(&plan->next_big, 1);
         __syncthreads();
         const int t = s_tile;
         __syncthreads();
-        if (t >= plan->nbig) break;
-        int n = 64;
-        while (n > plan->big_from && t >= plan->tile_end[n]) --n;
-        const int b = sorted[plan->item_start[n] + (t - plan->tile_start[n])];
+        if (t >= nbig) break;
+        const int n = vl_order_of(t, te, lo);
+        const int b = sorted[vl_lane_of(is, n) + (t - vl_lane_of(ts, n))];
         const int64_t o = offs[b];
         wpm_matrix<V, 64, OP_INV, METHOD, MIXED, VL_BIG_TPC>(a + o, x + o, n, true, n, n, ns_steps,
                                                              fill, info ? info + b : nullptr,
@@ -219,109 +238,255 @@ k_varlen_big(const V* __restrict__ a, V* x, const int64_t* __restrict__ offs,
 }
 
 // The last bucket for real float matrices by Cholesky without refinement:
-// one matrix per four-wave workgroup, padded to order 64 with the identity;
-// R and Y = R^{-1} by the sub-blocked routine of leaf_impl.hpp (the updates
-// on the matrix cores, five barriers per 16 columns instead of three per
-// row), then X = Y Y^T (the Section III.B product, whose leading operation
-// count equals Section IV's once R^{-1} skips its zero blocks) as upper 16 x 16
-// MFMA tiles, staged in LDS over R for row-major stores.
-constexpr int VL_LEAF_NB = 64;
+// one wave per matrix, padded to order 64 with the identity, no workgroup
+// barriers, nine matrices in flight per compute unit.  R and Y = R^{-1} by
+// 16-column sub-blocks: the diagonal sub-block in registers (one lane per
+// column, rows reach the other lanes by readlane), its panel row and the
+// trailing update as MFMA 16 x 16 x 4 tiles; then the off-diagonal blocks of
+// Y bottom-up, Y_{a,>a} = -Y_aa (R_{a,>a} Y_{>a,>a}), and X = Y Y^T (the
+// Section III.B product, whose leading operation count equals Section IV's
+// once R^{-1} skips its zero blocks), all as MFMA tiles.  One 64 x 68 LDS
+// array per wave: the upper triangle of A is overwritten by R above the
+// diagonal, while Y goes below it transposed (y_ij, i <= j, at row j, column
+// i); the diagonal of R is not kept, as only 1/r_ii, the diagonal of Y, is
+// used once a diagonal sub-block is done.  X then goes above the diagonal,
+// where R was: the off-diagonal tiles as they finish, the diagonal tiles
+// (which overwrite the diagonal of Y) last.  Row pitch 68 keeps the MFMA
+// operand reads of rows and of columns free of bank conflicts.  A is read
+// and X written as the dense n x n arrays they are (coalesced), and the next
+// matrix's index and offset are fetched while the current one runs.
+constexpr int VW_NB = 64, VW_LD = 68;
 template <int MIXED>
-constexpr size_t vl_leaf_smem()
+constexpr size_t vw_smem()
 {
-    return (size_t)2 * VL_LEAF_NB * lf_ld<float, VL_LEAF_NB>() * sizeof(float) +
-           VL_LEAF_NB * sizeof(double);
+    return (size_t)VW_NB * VW_LD * sizeof(float) + (MIXED ? VW_NB * sizeof(double) : 0);
 }
 
 template <int MIXED>
-__global__ void __launch_bounds__(LF_THREADS)
-k_varlen_leaf(const float* __restrict__ a, float* x, const int64_t* __restrict__ offs,
+__global__ void __launch_bounds__(64, 3)
+k_varlen_wave(const float* __restrict__ a, float* x, const int64_t* __restrict__ offs,
               const int32_t* __restrict__ sorted, VarlenPlan* plan, int fill,
               int32_t* __restrict__ info)
 {
-    constexpr int NB = VL_LEAF_NB, LD = lf_ld<float, NB>();
-    constexpr int NT = (NB / 16) * (NB / 16 + 1) / 2;       // upper 16 x 16 tiles of X
-    constexpr int TPW = (NT + 3) / 4;                        // tiles per wave
+    constexpr int NB = VW_NB, SB = LF_SB, LD = VW_LD, NSB = NB / SB;
     using Acc = typename mfma_acc<float>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    float* Rm = reinterpret_cast<float*>(smem_raw);          // R, then X (row major, upper)
-    float* Ym = Rm + NB * LD;                                // R^{-1}
-    double* dl = reinterpret_cast<double*>(Ym + NB * LD);    // FP64 pivot accumulators
-    __shared__ int s_tile, s_fail;
-    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
-    const int g = lane / 16, cc = lane % 16;
-    for (;;) {
-        if (tid == 0) s_tile = atomicAdd(&plan->next_big, 1);
-        __syncthreads();
-        const int t = s_tile;
-        __syncthreads();
-        if (t >= plan->nbig) break;
-        int n = 64;
-        while (n > plan->big_from && t >= plan->tile_end[n]) --n;
-        const int b = sorted[plan->item_start[n] + (t - plan->tile_start[n])];
-        const float* ab = a + offs[b];
-        float* xb = x + offs[b];
-        // upper triangle of A (identity beyond n); Y starts at zero
-        {
-            constexpr int PER = NB * NB / LF_THREADS;
-            float v[PER];
+    float* M = reinterpret_cast<float*>(smem_raw);
+    double* dl = reinterpret_cast<double*>(M + NB * LD);
+    const int lane = threadIdx.x, g = lane / 16, cc = lane % 16;
+    // y_ij of Y = R^{-1}, zero below its diagonal
+    auto Y = [&](int i, int j) { return i <= j ? M[j * LD + i] : 0.f; };
+    auto row = [&](int v) { return mfma_acc<float>::row(g, v); };
+    // one wave per workgroup: LDS writes by one lane reach the reads other
+    // lanes issue later in program order, so ordering needs no barrier, only
+    // that the compiler keeps LDS accesses on their side of this point
+    auto wave_sync = [] {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    const int te = plan->tile_end[lane + 1], ts = plan->tile_start[lane + 1];
+    const int is = plan->item_start[lane + 1];
+    const int nbig = plan->nbig, lo = plan->big_from;
+    auto grab = [&]() {
+        int v = 0;
+        if (lane == 0) v = atomicAdd(&plan->next_big, 1);
+        return __builtin_amdgcn_readfirstlane(v);
+    };
+    auto item = [&](int tt) {
+        const int nn = vl_order_of(tt, te, lo);
+        return sorted[vl_lane_of(is, nn) + (tt - vl_lane_of(ts, nn))];
+    };
+    // the next tile's matrix index and offset are fetched while this one runs
+    int t = grab(), b = 0;
+    int64_t o = 0;
+    if (t < nbig) {
+        b = item(t);
+        o = offs[b];
+    }
+    while (t < nbig) {
+        const int n = vl_order_of(t, te, lo);
+        const float* ab = a + o;
+        float* xb = x + o;
+        const int t2 = grab();
+        const int b2 = t2 < nbig ? item(t2) : 0;
+        // A in flight at once, element e = lane + 64 u of the dense n x n
+        // matrix; its upper triangle goes to LDS, the identity beyond n
+        const int nn = n * n;
+        const float rn = 1.f / (float)n;       // row e / n, exact for e < 4096
+        // an opaque copy of the lane index, so that the element indices below
+        // are not hoisted out of the loop (they would hold 64 registers each)
+        int li = lane;
+        asm volatile("" : "+v"(li));
+        wave_sync();                                     // the last matrix is stored
+        if (lane >= n)
+            for (int k = 0; k <= lane; ++k) M[k * LD + lane] = k == lane ? 1.f : 0.f;
+        for (int h = 0; h < 2; ++h) {
+            float v[NB / 2];
 #pragma unroll
-            for (int u = 0; u < PER; ++u) {
-                const int e = tid + LF_THREADS * u, k = e / NB, j = e % NB;
-                v[u] = (k == j) ? 1.f : 0.f;
-                if (j < n && k < n && k <= j) v[u] = ab[k * n + j];
+            for (int u = 0; u < NB / 2; ++u) {
+                const int e = li + 64 * u + 2048 * h;
+                v[u] = e < nn ? ab[e] : 0.f;
             }
 #pragma unroll
-            for (int u = 0; u < PER; ++u) {
-                const int e = tid + LF_THREADS * u, k = e / NB, j = e % NB;
-                Rm[k * LD + j] = (k <= j) ? v[u] : 0.f;
-                Ym[k * LD + j] = 0.f;
-            }
-        }
-        if (MIXED)
-            for (int j = tid; j < NB; j += LF_THREADS) dl[j] = (j < n) ? (double)ab[j * n + j] : 1.0;
-        __syncthreads();
-        const int f = lf_factor_inverse<float, NB, MIXED>(Rm, Ym, dl, n);
-        if (tid == 0) s_fail = f;
-        // X = Y Y^T: x_ij = sum_{k >= j} y_ik y_jk (i <= j), tile (tr, tc) from k = 16 tc
-        Acc xa[TPW];
-#pragma unroll
-        for (int u = 0; u < TPW; ++u) {
-            xa[u] = Acc{0, 0, 0, 0};
-            const int q = wave + 4 * u;
-            if (q < NT) {
-                int tr = 0, rem = q;
-                while (rem >= NB / 16 - tr) { rem -= NB / 16 - tr; ++tr; }
-                const int tc = tr + rem;
-                lf_tile<float>(xa[u], NB - 16 * tc, g, cc,
-                               [&](int r, int k) { return Ym[(16 * tr + r) * LD + 16 * tc + k]; },
-                               [&](int k, int c) { return Ym[(16 * tc + c) * LD + 16 * tc + k]; });
-            }
-        }
-        __syncthreads();                                     // R is no longer read
-#pragma unroll
-        for (int u = 0; u < TPW; ++u) {
-            const int q = wave + 4 * u;
-            if (q < NT) {
-                int tr = 0, rem = q;
-                while (rem >= NB / 16 - tr) { rem -= NB / 16 - tr; ++tr; }
-                const int tc = tr + rem;
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    Rm[(16 * tr + mfma_acc<float>::row(g, v)) * LD + 16 * tc + cc] = xa[u][v];
+            for (int u = 0; u < NB / 2; ++u) {
+                const int e = li + 64 * u + 2048 * h;
+                const int k = (int)(((float)e + 0.5f) * rn), j = e - k * n;
+                if (e < nn && k <= j) M[k * LD + j] = v[u];
             }
         }
-        __syncthreads();
-        const int fl = s_fail;
-        for (int e = tid; e < n * n; e += LF_THREADS) {
-            const int i = e / n, j = e % n;
-            if (j >= i || fill) {
-                const float v = (j >= i) ? Rm[i * LD + j] : Rm[j * LD + i];
-                xb[e] = fl ? __builtin_nanf("") : v;
+        wave_sync();
+        if (MIXED) dl[lane] = lane < n ? (double)M[lane * LD + lane] : 1.0;
+        int fail = 0;
+        for (int bb = 0; bb < NSB; ++bb) {
+            const int b0 = bb * SB, b1 = b0 + SB, nr = NB - b1;
+            // ---- diagonal sub-block in registers, one lane per column
+            {
+                const int j = lane;                          // column b0 + j (lanes >= SB idle)
+                float c[SB];
+#pragma unroll
+                for (int k = 0; k < SB; ++k)
+                    c[k] = (j < SB && k <= j) ? M[(b0 + k) * LD + b0 + j] : 0.f;
+                double dj = (MIXED && j < SB) ? dl[b0 + j] : 0.0;
+                float sv[SB];                                // 1/r_kk, uniform
+#pragma unroll
+                for (int i = 0; i < SB; ++i) {
+                    const double piv = MIXED ? dj : (double)c[i];
+                    double r, yv;
+                    sqrt_rsqrt_est(piv, r, yv);
+                    const int okl = (piv > 0.0 && piv < __builtin_inf()) ? 1 : 0;
+                    const int ok = __builtin_amdgcn_readlane(okl, i);
+                    if (!ok && !fail && b0 + i < n) fail = b0 + i + 1;
+                    const float s_i = lf_bcast((float)yv, i), r_ii = lf_bcast((float)r, i);
+                    sv[i] = s_i;
+                    c[i] = (j > i) ? c[i] * s_i : ((j == i) ? r_ii : c[i]);
+                    if (MIXED && j > i) dj = fma(-(double)c[i], (double)c[i], dj);
+#pragma unroll
+                    for (int k = i + 1; k < SB; ++k) c[k] -= lf_bcast(c[i], k) * c[i];
+                }
+                float y[SB];                                 // column j of Y_bb, bottom-up
+#pragma unroll
+                for (int k = SB - 1; k >= 0; --k) {
+                    float acc = 0.f;
+#pragma unroll
+                    for (int m = k + 1; m < SB; ++m) acc += lf_bcast(c[k], m) * y[m];
+                    y[k] = (j > k) ? -sv[k] * acc : ((j == k) ? sv[k] : 0.f);
+                }
+                if (j < SB) {
+#pragma unroll
+                    for (int k = 0; k < SB; ++k) {
+                        if (k < j) M[(b0 + k) * LD + b0 + j] = c[k];
+                        if (k <= j) M[(b0 + j) * LD + b0 + k] = y[k];
+                    }
+                }
+            }
+            wave_sync();
+            if (nr == 0) break;
+            // ---- panel row R_{b,>b} = Y_bb^T A_{b,>b}, one column tile at a time
+            const int ptn = nr / 16;
+            for (int tc = 0; tc < ptn; ++tc) {
+                Acc d = Acc{0, 0, 0, 0};
+                lf_tile<float>(d, SB, g, cc, [&](int r, int k) { return Y(b0 + k, b0 + r); },
+                               [&](int k, int cl) { return M[(b0 + k) * LD + b1 + 16 * tc + cl]; });
+#pragma unroll
+                for (int v = 0; v < 4; ++v) M[(b0 + row(v)) * LD + b1 + 16 * tc + cc] = d[v];
+            }
+            wave_sync();
+            // ---- FP64 pivots of the remaining columns, and the upper part of
+            // A_{>b,>b} -= R_{b,>b}^T R_{b,>b}
+            if (MIXED) {
+                for (int jj = lane; jj < nr; jj += 64) {
+                    double q = dl[b1 + jj];
+#pragma unroll 8
+                    for (int k = 0; k < SB; ++k) {
+                        const double v = (double)M[(b0 + k) * LD + b1 + jj];
+                        q = fma(-v, v, q);
+                    }
+                    dl[b1 + jj] = q;
+                }
+            }
+            for (int tr = 0; tr < ptn; ++tr) {
+                for (int tc = tr; tc < ptn; ++tc) {
+                    Acc d = Acc{0, 0, 0, 0};
+                    lf_tile<float>(d, SB, g, cc,
+                                   [&](int r, int k) { return M[(b0 + k) * LD + b1 + 16 * tr + r]; },
+                                   [&](int k, int cl) { return M[(b0 + k) * LD + b1 + 16 * tc + cl]; });
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int i = b1 + 16 * tr + row(v), jc = b1 + 16 * tc + cc;
+                        if (jc >= i) M[i * LD + jc] -= d[v];
+                    }
+                }
+            }
+            wave_sync();
+        }
+        // ---- off-diagonal blocks of Y, block rows bottom-up, one column tile
+        // at a time: T = R_{a,>a} Y_{>a,>a}, then Y_{a,>a} = -Y_aa T
+        for (int aa = NSB - 2; aa >= 0; --aa) {
+            const int a0 = aa * SB, b1 = a0 + SB, ptn = (NB - b1) / 16;
+            for (int tc = 0; tc < ptn; ++tc) {
+                const int c0 = b1 + 16 * tc;
+                Acc d = Acc{0, 0, 0, 0};
+                lf_tile<float>(d, 16 * (tc + 1), g, cc,
+                               [&](int r, int k) { return M[(a0 + r) * LD + b1 + k]; },
+                               [&](int k, int cl) { return Y(b1 + k, c0 + cl); });
+#pragma unroll
+                for (int v = 0; v < 4; ++v) M[(c0 + cc) * LD + a0 + row(v)] = d[v];
+                wave_sync();
+                Acc e = Acc{0, 0, 0, 0};
+                lf_tile<float>(e, SB, g, cc, [&](int r, int k) { return Y(a0 + r, a0 + k); },
+                               [&](int k, int cl) { return M[(c0 + cl) * LD + a0 + k]; });
+#pragma unroll
+                for (int v = 0; v < 4; ++v) M[(c0 + cc) * LD + a0 + row(v)] = -e[v];
+                wave_sync();
             }
         }
-        if (tid == 0 && info) info[b] = fl;
-        __syncthreads();                                     // LDS free for the next matrix
+        const int64_t o2 = t2 < nbig ? offs[b2] : 0;
+        // ---- X = Y Y^T: x_ij = sum_{k >= j} y_ik y_jk (i <= j); tile (tr, tc)
+        // sums from k = 16 tc
+        Acc xd[NSB];
+#pragma unroll
+        for (int tc = 0; tc < NSB; ++tc) {
+#pragma unroll
+            for (int tr = 0; tr <= tc; ++tr) {
+                Acc d = Acc{0, 0, 0, 0};
+                lf_tile<float>(d, NB - 16 * tc, g, cc,
+                               [&](int r, int k) { return Y(16 * tr + r, 16 * tc + k); },
+                               [&](int k, int cl) { return Y(16 * tc + cl, 16 * tc + k); });
+                if (tr < tc) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) M[(16 * tr + row(v)) * LD + 16 * tc + cc] = d[v];
+                } else {
+                    xd[tc] = d;
+                }
+            }
+        }
+        wave_sync();
+#pragma unroll
+        for (int tq = 0; tq < NSB; ++tq) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * tq + row(v), jc = 16 * tq + cc;
+                if (jc >= i) M[i * LD + jc] = xd[tq][v];
+            }
+        }
+        wave_sync();
+        // rows of X, all read from LDS before the stores
+        // coalesced: element e = lane + 64 u of the dense n x n result
+        // coalesced: element e = lane + 64 u of the dense n x n result
+        li = lane;
+        asm volatile("" : "+v"(li));
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int e = li + 64 * u, ee = e < nn ? e : 0;
+            const int i = (int)(((float)ee + 0.5f) * rn), j = ee - i * n;
+            const float w = j >= i ? M[i * LD + j] : M[j * LD + i];
+            if (e < nn && (j >= i || fill)) xb[e] = fail ? __builtin_nanf("") : w;
+        }
+        if (lane == 0 && info) info[b] = fail;
+        t = t2;
+        b = b2;
+        o = o2;
     }
 }
 
@@ -369,18 +534,10 @@ static hipError_t varlen_run(int64_t batch, const int32_t* n_dev, const int64_t*
         if constexpr (std::is_same<V, float>::value && METHOD == 0) {
             leaf = !MIXED || ns_steps == 0;
             if (leaf) {
-                auto kl = k_varlen_leaf<MIXED>;
-                constexpr size_t sl = vl_leaf_smem<MIXED>();
-                static bool lattr = false;
-                if (!lattr) {
-                    e = hipFuncSetAttribute((const void*)kl,
-                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sl);
-                    if (e != hipSuccess) return e;
-                    lattr = true;
-                }
-                hipLaunchKernelGGL(kl, dim3((unsigned)grid_of((const void*)kl, LF_THREADS, sl)),
-                                   dim3(LF_THREADS), sl, s, (const float*)a, (float*)x, off_dev,
-                                   sorted, plan, fill, info);
+                auto kw = k_varlen_wave<MIXED>;
+                constexpr size_t sw = vw_smem<MIXED>();
+                hipLaunchKernelGGL(kw, dim3((unsigned)grid_of((const void*)kw, 64, sw)), dim3(64), sw,
+                                   s, (const float*)a, (float*)x, off_dev, sorted, plan, fill, info);
             }
         }
         if (!leaf)

@@ -147,14 +147,17 @@ def test_varlen_last_bucket_edge_cases(prec, method, fill):
         assert err <= TOL_FP32 * O.kappa2(a), "order %d err %.3e" % (n, err)
 
 
-def test_varlen_graph_capture_replays_match_eager():
+@pytest.mark.parametrize("prec,ns", [("mixed", 1), ("plain", 0)])
+def test_varlen_graph_capture_replays_match_eager(prec, ns):
+    """Refined mixed precision (four-lane LDS route for the last bucket) and
+    plain FP32 (one wave per matrix on the matrix cores)."""
     t = torch_cuda()
     from paper_1111_4144_amd import api
     packed, sizes, offs = G.varlen_spd(2000, seed=22)
     P = t.from_numpy(packed).cuda()
     S = t.from_numpy(sizes).cuda()
     F = t.from_numpy(offs).cuda()
-    eager = api.inverse_varlen(P, S, F, n_max=64, precision="mixed", ns_steps=1)
+    eager = api.inverse_varlen(P, S, F, n_max=64, precision=prec, ns_steps=ns)
     out = t.empty_like(P)
     from paper_1111_4144_amd import _lib as L
     import ctypes
@@ -163,11 +166,11 @@ def test_varlen_graph_capture_replays_match_eager():
     s = t.cuda.Stream()
     s.wait_stream(t.cuda.current_stream())
     with t.cuda.stream(s):                            # warm-up outside the capture
-        api.inverse_varlen(P, S, F, n_max=64, precision="mixed", ns_steps=1, out=out, workspace=work)
+        api.inverse_varlen(P, S, F, n_max=64, precision=prec, ns_steps=ns, out=out, workspace=work)
     t.cuda.current_stream().wait_stream(s)
     g = t.cuda.CUDAGraph()
     with t.cuda.graph(g):
-        api.inverse_varlen(P, S, F, n_max=64, precision="mixed", ns_steps=1, out=out, workspace=work)
+        api.inverse_varlen(P, S, F, n_max=64, precision=prec, ns_steps=ns, out=out, workspace=work)
     for r in range(3):
         out.fill_(float("nan"))
         junk = api.inverse_varlen(P, S, F, n_max=64)   # eager work between replays
