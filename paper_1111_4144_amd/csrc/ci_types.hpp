@@ -142,6 +142,15 @@ CI_D void sqrt_rsqrt_est(float v, float& r, float& s)
     s = __builtin_amdgcn_rsqf(v);
     r = v * s;
 }
+// FP32 square root and its reciprocal from the hardware estimate and one
+// Newton step on the reciprocal, y <- y + y (1 - v y^2) / 2 (about 1 ulp).
+CI_D void sqrt_rsqrt_nr(float v, float& r, float& s)
+{
+    const float y = __builtin_amdgcn_rsqf(v);
+    const float e = fmaf(-(v * y), y, 1.f);
+    s = fmaf(0.5f * y, e, y);
+    r = v * s;
+}
 CI_D double rcp_est(double v)
 {
     const double y = __builtin_amdgcn_rcp(v);

@@ -351,26 +351,40 @@ k_varlen_wave(const float* __restrict__ a, float* x, const int64_t* __restrict__
                 float sv[SB];                                // 1/r_kk, uniform
 #pragma unroll
                 for (int i = 0; i < SB; ++i) {
-                    const double piv = MIXED ? dj : (double)c[i];
-                    double r, yv;
-                    sqrt_rsqrt_est(piv, r, yv);
-                    const int okl = (piv > 0.0 && piv < __builtin_inf()) ? 1 : 0;
-                    const int ok = __builtin_amdgcn_readlane(okl, i);
+                    // the pivot reaches every lane first, so the square
+                    // root needs no broadcast after it
+                    float s_i, r_ii;
+                    bool ok;
+                    if constexpr (MIXED) {
+                        const double piv = lf_bcast(dj, i);
+                        double r, yv;
+                        sqrt_rsqrt_est(piv, r, yv);
+                        ok = piv > 0.0 && piv < __builtin_inf();
+                        s_i = (float)yv;
+                        r_ii = (float)r;
+                    } else {
+                        const float piv = lf_bcast(c[i], i);
+                        sqrt_rsqrt_nr(piv, r_ii, s_i);
+                        ok = piv > 0.f && piv < __builtin_inff();
+                    }
                     if (!ok && !fail && b0 + i < n) fail = b0 + i + 1;
-                    const float s_i = lf_bcast((float)yv, i), r_ii = lf_bcast((float)r, i);
                     sv[i] = s_i;
                     c[i] = (j > i) ? c[i] * s_i : ((j == i) ? r_ii : c[i]);
                     if (MIXED && j > i) dj = fma(-(double)c[i], (double)c[i], dj);
 #pragma unroll
                     for (int k = i + 1; k < SB; ++k) c[k] -= lf_bcast(c[i], k) * c[i];
                 }
-                float y[SB];                                 // column j of Y_bb, bottom-up
+                // column j of Y_bb bottom-up, y_kj = -s_k sum_{m > k} r_km y_mj,
+                // each y_mj added to every row above it as soon as it is known
+                // (two dependent operations per row instead of a serial sum)
+                float y[SB], acc[SB];
 #pragma unroll
-                for (int k = SB - 1; k >= 0; --k) {
-                    float acc = 0.f;
+                for (int k = 0; k < SB; ++k) acc[k] = 0.f;
 #pragma unroll
-                    for (int m = k + 1; m < SB; ++m) acc += lf_bcast(c[k], m) * y[m];
-                    y[k] = (j > k) ? -sv[k] * acc : ((j == k) ? sv[k] : 0.f);
+                for (int m = SB - 1; m >= 0; --m) {
+                    y[m] = (j > m) ? -sv[m] * acc[m] : ((j == m) ? sv[m] : 0.f);
+#pragma unroll
+                    for (int k = 0; k < m; ++k) acc[k] += lf_bcast(c[k], m) * y[m];
                 }
                 if (j < SB) {
 #pragma unroll
