@@ -13,9 +13,10 @@
 // float by Cholesky without refinement, else four waves with four lanes per
 // column (LDS-resident).  The edge of the last bucket (33) can move down to 25
 // or 17 (a tuned choice): those orders then go to the last bucket's kernel.
-// Two persistent kernels, one per block shape, take tiles from their own
-// atomic counters until none are left (every wave reaches that exit): first
-// the last bucket, then the rest, largest orders first within each.  The
+// Persistent kernels take tiles from their own atomic counters until none
+// are left (every wave reaches that exit): first the last bucket (one kernel,
+// or on the matrix cores one per padded order 64, 48 and 32), then the rest,
+// largest orders first within each.  The
 // order of a tile comes from the plan's per-order table held one order per
 // lane (a ballot, no dependent loads).  Results do not depend on which wave
 // takes which tile.
@@ -31,7 +32,9 @@ namespace ci {
 struct VarlenPlan {
     int next;              // tile counter of the orders <= 32 kernel (starts at nbig)
     int ntiles;
-    int next_big;          // tile counter of the last bucket's kernel (starts at 0)
+    int next_big;          // tile counter of the last bucket's orders 49..64 (starts at 0)
+    int next_48;           // the same for its orders 33..48 (starts at tile_end[49])
+    int next_32;           // the same for its orders up to 32 (starts at tile_end[33])
     int nbig;              // tiles of orders big_from..64 (one matrix each, first in the order)
     int big_from;          // smallest order of the four-waves-per-matrix kernel (17, 25 or 33)
     int count[65];         // matrices per order
@@ -103,6 +106,8 @@ __global__ void k_vl_scan(VarlenPlan* plan, int big_from)
     plan->nbig = plan->tile_end[big_from];
     plan->next = plan->nbig;
     plan->next_big = 0;
+    plan->next_48 = plan->tile_end[49];
+    plan->next_32 = plan->tile_end[33];
 }
 
 // Each block reserves one contiguous range per order with a single global
@@ -238,14 +243,15 @@ k_varlen_big(const V* __restrict__ a, V* x, const int64_t* __restrict__ offs,
 }
 
 // The last bucket for real float matrices by Cholesky without refinement:
-// one wave per matrix, padded to order 64 with the identity, no workgroup
-// barriers, nine matrices in flight per compute unit.  R and Y = R^{-1} by
+// one wave per matrix, padded with the identity to order NB (64, 48 or 32,
+// one launch each), no workgroup barriers, nine to eighteen matrices in
+// flight per compute unit.  R and Y = R^{-1} by
 // 16-column sub-blocks: the diagonal sub-block in registers (one lane per
 // column, rows reach the other lanes by readlane), its panel row and the
 // trailing update as MFMA 16 x 16 x 4 tiles; then the off-diagonal blocks of
 // Y bottom-up, Y_{a,>a} = -Y_aa (R_{a,>a} Y_{>a,>a}), and X = Y Y^T (the
 // Section III.B product, whose leading operation count equals Section IV's
-// once R^{-1} skips its zero blocks), all as MFMA tiles.  One 64 x 68 LDS
+// once R^{-1} skips its zero blocks), all as MFMA tiles.  One NB x 68 LDS
 // array per wave: the upper triangle of A is overwritten by R above the
 // diagonal, while Y goes below it transposed (y_ij, i <= j, at row j, column
 // i); the diagonal of R is not kept, as only 1/r_ii, the diagonal of Y, is
@@ -255,20 +261,26 @@ k_varlen_big(const V* __restrict__ a, V* x, const int64_t* __restrict__ offs,
 // operand reads of rows and of columns free of bank conflicts.  A is read
 // and X written as the dense n x n arrays they are (coalesced), and the next
 // matrix's index and offset are fetched while the current one runs.
-constexpr int VW_NB = 64, VW_LD = 68;
-template <int MIXED>
+constexpr int VW_LD = 68;
+template <int NB, int MIXED>
 constexpr size_t vw_smem()
 {
-    return (size_t)VW_NB * VW_LD * sizeof(float) + (MIXED ? VW_NB * sizeof(double) : 0);
+    return (size_t)NB * VW_LD * sizeof(float) + (MIXED ? NB * sizeof(double) : 0);
 }
 
-template <int MIXED>
+// NB = 64 takes the orders 49..64 (tiles [0, tile_end[49]), counter
+// next_big), NB = 48 the orders 33..48 and NB = 32 those below 33 when the
+// bucket starts there: less work per matrix and smaller LDS arrays, so
+// twelve and sixteen waves per compute unit instead of nine.
+template <int NB, int MIXED>
 __global__ void __launch_bounds__(64, 3)
 k_varlen_wave(const float* __restrict__ a, float* x, const int64_t* __restrict__ offs,
               const int32_t* __restrict__ sorted, VarlenPlan* plan, int fill,
               int32_t* __restrict__ info)
 {
-    constexpr int NB = VW_NB, SB = LF_SB, LD = VW_LD, NSB = NB / SB;
+    static_assert(NB == 64 || NB == 48 || NB == 32, "padded order");
+    constexpr int SB = LF_SB, LD = VW_LD, NSB = NB / SB;
+    constexpr int EH = (NB * NB / 64 + 1) / 2;       // elements a lane loads per half
     using Acc = typename mfma_acc<float>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     float* M = reinterpret_cast<float*>(smem_raw);
@@ -287,10 +299,13 @@ k_varlen_wave(const float* __restrict__ a, float* x, const int64_t* __restrict__
     };
     const int te = plan->tile_end[lane + 1], ts = plan->tile_start[lane + 1];
     const int is = plan->item_start[lane + 1];
-    const int nbig = plan->nbig, lo = plan->big_from;
+    const int lo = plan->big_from;
+    // end of this kernel's tile range and its counter
+    const int nbig = NB == 64 ? vl_lane_of(te, 49) : NB == 48 ? vl_lane_of(te, 33) : plan->nbig;
+    int* const counter = NB == 64 ? &plan->next_big : NB == 48 ? &plan->next_48 : &plan->next_32;
     auto grab = [&]() {
         int v = 0;
-        if (lane == 0) v = atomicAdd(&plan->next_big, 1);
+        if (lane == 0) v = atomicAdd(counter, 1);
         return __builtin_amdgcn_readfirstlane(v);
     };
     auto item = [&](int tt) {
@@ -319,24 +334,24 @@ k_varlen_wave(const float* __restrict__ a, float* x, const int64_t* __restrict__
         int li = lane;
         asm volatile("" : "+v"(li));
         wave_sync();                                     // the last matrix is stored
-        if (lane >= n)
+        if (lane >= n && lane < NB)
             for (int k = 0; k <= lane; ++k) M[k * LD + lane] = k == lane ? 1.f : 0.f;
         for (int h = 0; h < 2; ++h) {
-            float v[NB / 2];
+            float v[EH];
 #pragma unroll
-            for (int u = 0; u < NB / 2; ++u) {
-                const int e = li + 64 * u + 2048 * h;
+            for (int u = 0; u < EH; ++u) {
+                const int e = li + 64 * (u + EH * h);
                 v[u] = e < nn ? ab[e] : 0.f;
             }
 #pragma unroll
-            for (int u = 0; u < NB / 2; ++u) {
-                const int e = li + 64 * u + 2048 * h;
+            for (int u = 0; u < EH; ++u) {
+                const int e = li + 64 * (u + EH * h);
                 const int k = (int)(((float)e + 0.5f) * rn), j = e - k * n;
                 if (e < nn && k <= j) M[k * LD + j] = v[u];
             }
         }
         wave_sync();
-        if (MIXED) dl[lane] = lane < n ? (double)M[lane * LD + lane] : 1.0;
+        if (MIXED && lane < NB) dl[lane] = lane < n ? (double)M[lane * LD + lane] : 1.0;
         int fail = 0;
         for (int bb = 0; bb < NSB; ++bb) {
             const int b0 = bb * SB, b1 = b0 + SB, nr = NB - b1;
@@ -491,7 +506,7 @@ k_varlen_wave(const float* __restrict__ a, float* x, const int64_t* __restrict__
         li = lane;
         asm volatile("" : "+v"(li));
 #pragma unroll
-        for (int u = 0; u < NB; ++u) {
+        for (int u = 0; u < 2 * EH; ++u) {
             const int e = li + 64 * u, ee = e < nn ? e : 0;
             const int i = (int)(((float)ee + 0.5f) * rn), j = ee - i * n;
             const float w = j >= i ? M[i * LD + j] : M[j * LD + i];
@@ -548,10 +563,21 @@ static hipError_t varlen_run(int64_t batch, const int32_t* n_dev, const int64_t*
         if constexpr (std::is_same<V, float>::value && METHOD == 0) {
             leaf = !MIXED || ns_steps == 0;
             if (leaf) {
-                auto kw = k_varlen_wave<MIXED>;
-                constexpr size_t sw = vw_smem<MIXED>();
+                auto kw = k_varlen_wave<64, MIXED>;
+                constexpr size_t sw = vw_smem<64, MIXED>();
                 hipLaunchKernelGGL(kw, dim3((unsigned)grid_of((const void*)kw, 64, sw)), dim3(64), sw,
                                    s, (const float*)a, (float*)x, off_dev, sorted, plan, fill, info);
+                auto km = k_varlen_wave<48, MIXED>;
+                constexpr size_t sm = vw_smem<48, MIXED>();
+                hipLaunchKernelGGL(km, dim3((unsigned)grid_of((const void*)km, 64, sm)), dim3(64), sm,
+                                   s, (const float*)a, (float*)x, off_dev, sorted, plan, fill, info);
+                if (big_from < 33) {
+                    auto ks = k_varlen_wave<32, MIXED>;
+                    constexpr size_t ss = vw_smem<32, MIXED>();
+                    hipLaunchKernelGGL(ks, dim3((unsigned)grid_of((const void*)ks, 64, ss)), dim3(64),
+                                       ss, s, (const float*)a, (float*)x, off_dev, sorted, plan, fill,
+                                       info);
+                }
             }
         }
         if (!leaf)
