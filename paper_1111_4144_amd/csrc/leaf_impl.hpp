@@ -74,36 +74,39 @@ __device__ int lf_factor_inverse(T* __restrict__ Rm, T* __restrict__ Ym, double*
             T sv[SB];                                 // 1/r_kk, uniform
 #pragma unroll
             for (int i = 0; i < SB; ++i) {
-                const double piv = MIXED ? dj : (double)c[i];
-                T rii, si;
+                // the pivot reaches every lane first, so its square root needs
+                // no broadcast after it
+                const double piv = MIXED ? lf_bcast(dj, i) : (double)lf_bcast(c[i], i);
+                T r_ii, s_i;
                 if constexpr (sizeof(T) == 4) {
                     double r, y;
                     sqrt_rsqrt_est(piv, r, y);
-                    rii = (T)r;
-                    si = (T)y;
+                    r_ii = (T)r;
+                    s_i = (T)y;
                 } else {
                     const double r = sqrt(piv);
-                    rii = (T)r;
-                    si = (T)(1.0 / r);
+                    r_ii = (T)r;
+                    s_i = (T)(1.0 / r);
                 }
-                const int okl = (piv > 0.0 && piv < __builtin_inf()) ? 1 : 0;
-                const int ok = __builtin_amdgcn_readlane(okl, i);
+                const bool ok = piv > 0.0 && piv < __builtin_inf();
                 if (!ok && !fail && b0 + i < nl) fail = b0 + i + 1;
-                const T s_i = lf_bcast(si, i), r_ii = lf_bcast(rii, i);
                 sv[i] = s_i;
                 c[i] = (j > i) ? c[i] * s_i : ((j == i) ? r_ii : c[i]);
                 if (MIXED && j > i) dj = fma(-(double)c[i], (double)c[i], dj);
 #pragma unroll
                 for (int k = i + 1; k < SB; ++k) c[k] -= lf_bcast(c[i], k) * c[i];
             }
-            // Y_bb: column j by back-substitution, rows j-1 .. 0
-            T y[SB];
+            // Y_bb: column j bottom-up, y_kj = -s_k sum_{m > k} r_km y_mj, each
+            // y_mj added to every row above it as soon as it is known (two
+            // dependent operations per row instead of a serial sum)
+            T y[SB], acc[SB];
 #pragma unroll
-            for (int k = SB - 1; k >= 0; --k) {
-                T acc = T(0);
+            for (int k = 0; k < SB; ++k) acc[k] = T(0);
 #pragma unroll
-                for (int m = k + 1; m < SB; ++m) acc += lf_bcast(c[k], m) * y[m];
-                y[k] = (j > k) ? -sv[k] * acc : ((j == k) ? sv[k] : T(0));
+            for (int m = SB - 1; m >= 0; --m) {
+                y[m] = (j > m) ? -sv[m] * acc[m] : ((j == m) ? sv[m] : T(0));
+#pragma unroll
+                for (int k = 0; k < m; ++k) acc[k] += lf_bcast(c[k], m) * y[m];
             }
             if (j < SB) {
 #pragma unroll
