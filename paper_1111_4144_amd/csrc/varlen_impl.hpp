@@ -7,8 +7,8 @@
 //              in the sorted index list and its tile range;
 //   3. scatter every matrix index into the sorted list.
 // Tiles: an order n <= 8 tile is up to 64 matrices (one lane each, registers);
-// 9..16 up to 4 matrices (16-lane groups padded to 16 with the identity,
-// which leaves the n x n block exact); 17..32 up to 2 (LDS-resident, one lane
+// 9..16 up to 16 or 4 matrices (4- or 16-lane groups padded to 16 with the
+// identity, which leaves the n x n block exact); 17..32 up to 2 (LDS-resident, one lane
 // per column) and 33..64 one matrix: one wave on the matrix cores for real
 // float by Cholesky without refinement, else four waves with four lanes per
 // column (LDS-resident).  The edge of the last bucket (33) can move down to 25
@@ -44,7 +44,12 @@ struct VarlenPlan {
     int cursor[65];        // scatter cursors
 };
 
-CI_D int vl_tile_size(int n) { return n <= 8 ? 64 : n <= 16 ? 4 : n <= 32 ? 2 : 1; }
+// Lanes per matrix of orders 9..16: four (sixteen matrices a wave) for real
+// float without refinement, else sixteen (four a wave; the four-lane form's
+// registers would also cap the other orders' occupancy there).
+template <class V, int MIXED>
+constexpr int vl_g16() { return (std::is_same<V, float>::value && !MIXED) ? 4 : 16; }
+CI_D int vl_tile_size(int n, int g16) { return n <= 8 ? 64 : n <= 16 ? 64 / g16 : n <= 32 ? 2 : 1; }
 
 // Order of tile t.  Tiles run largest order first, so the orders whose tile
 // range ends at or before t form the top of (lo, 64]; lane l of the wave holds
@@ -88,14 +93,14 @@ k_vl_count(const int32_t* __restrict__ ns, int64_t batch, int nmax, VarlenPlan* 
         if (local[t]) atomicAdd(&plan->count[t], local[t]);
 }
 
-__global__ void k_vl_scan(VarlenPlan* plan, int big_from)
+__global__ void k_vl_scan(VarlenPlan* plan, int big_from, int g16)
 {
     if (threadIdx.x != 0) return;
     int items = 0, tiles = 0;
     plan->big_from = big_from;
     for (int n = 64; n >= 1; --n) {
         const int c = plan->count[n];
-        const int ts = n >= big_from ? 1 : vl_tile_size(n);
+        const int ts = n >= big_from ? 1 : vl_tile_size(n, g16);
         plan->item_start[n] = items;
         plan->tile_start[n] = tiles;
         tiles += (c + ts - 1) / ts;
@@ -153,6 +158,7 @@ k_varlen(const V* __restrict__ a, V* x, const int64_t* __restrict__ offs,
          const int32_t* __restrict__ sorted, VarlenPlan* plan, int ns_steps, int fill,
          int32_t* __restrict__ info)
 {
+    constexpr int G16 = vl_g16<V, MIXED>();
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int s_tile;
     const int lane = threadIdx.x;
@@ -167,7 +173,7 @@ k_varlen(const V* __restrict__ a, V* x, const int64_t* __restrict__ offs,
         __syncthreads();
         if (t >= ntiles) break;
         const int n = vl_order_of(t, te, 1);
-        const int per = vl_tile_size(n);
+        const int per = vl_tile_size(n, G16);
         const int k = t - vl_lane_of(ts, n);
         const int first = vl_lane_of(is, n) + k * per;
         const int cnt = min(per, vl_lane_of(ct, n) - k * per);
@@ -189,14 +195,14 @@ k_varlen(const V* __restrict__ a, V* x, const int64_t* __restrict__ offs,
                 if (info) info[b] = f;
             }
         } else if (n <= 16) {
-            const int g = lane / 16;
+            const int g = lane / G16;
             const bool valid = g < cnt;
             const int b = sorted[first + (valid ? g : 0)];
             const int64_t o = offs[b];
-            group_matrix<V, 16, 16, OP_INV, METHOD, MIXED>(a + o, n, n, x + o, n, valid, fill,
-                                                           ns_steps, lane % 16,
-                                                           (valid && info) ? info + b : nullptr,
-                                                           nullptr);
+            group_matrix<V, 16, G16, OP_INV, METHOD, MIXED>(a + o, n, n, x + o, n, valid, fill,
+                                                            ns_steps, lane % G16,
+                                                            (valid && info) ? info + b : nullptr,
+                                                            nullptr);
         } else {
             const int g = lane / 32;
             const bool valid = g < cnt;
@@ -532,7 +538,7 @@ static hipError_t varlen_run(int64_t batch, const int32_t* n_dev, const int64_t*
     const unsigned gb = (unsigned)((batch + 255) / 256);
     hipLaunchKernelGGL(k_vl_init, dim3(1), dim3(256), 0, s, plan);
     hipLaunchKernelGGL(k_vl_count, dim3(gb), dim3(256), 0, s, n_dev, batch, n_max, plan, info);
-    hipLaunchKernelGGL(k_vl_scan, dim3(1), dim3(64), 0, s, plan, big_from);
+    hipLaunchKernelGGL(k_vl_scan, dim3(1), dim3(64), 0, s, plan, big_from, vl_g16<V, MIXED>());
     hipLaunchKernelGGL(k_vl_scatter, dim3(gb), dim3(256), 0, s, n_dev, batch, n_max, plan, sorted);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
