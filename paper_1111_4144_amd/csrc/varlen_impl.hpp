@@ -286,7 +286,6 @@ k_varlen_wave(const float* __restrict__ a, float* x, const int64_t* __restrict__
 {
     static_assert(NB == 64 || NB == 48 || NB == 32, "padded order");
     constexpr int SB = LF_SB, LD = VW_LD, NSB = NB / SB;
-    constexpr int EH = (NB * NB / 64 + 1) / 2;       // elements a lane loads per half
     using Acc = typename mfma_acc<float>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     float* M = reinterpret_cast<float*>(smem_raw);
@@ -331,29 +330,27 @@ k_varlen_wave(const float* __restrict__ a, float* x, const int64_t* __restrict__
         float* xb = x + o;
         const int t2 = grab();
         const int b2 = t2 < nbig ? item(t2) : 0;
-        // A in flight at once, element e = lane + 64 u of the dense n x n
-        // matrix; its upper triangle goes to LDS, the identity beyond n
-        const int nn = n * n;
-        const float rn = 1.f / (float)n;       // row e / n, exact for e < 4096
-        // an opaque copy of the lane index, so that the element indices below
-        // are not hoisted out of the loop (they would hold 64 registers each)
-        int li = lane;
-        asm volatile("" : "+v"(li));
+        // rows of A (row k in lanes j < n, one uniform base address per row),
+        // half of them in flight at once; their upper triangle goes to LDS,
+        // the identity beyond n.  The lane index goes through an opaque copy
+        // so that the per-row masks and addresses are not hoisted out of the
+        // loop (they would hold registers for the whole kernel).
         wave_sync();                                     // the last matrix is stored
-        if (lane >= n && lane < NB)
-            for (int k = 0; k <= lane; ++k) M[k * LD + lane] = k == lane ? 1.f : 0.f;
-        for (int h = 0; h < 2; ++h) {
-            float v[EH];
+        {
+            int li = lane;
+            asm volatile("" : "+v"(li));
+            for (int h = 0; h < 2; ++h) {
+                float v[NB / 2];
 #pragma unroll
-            for (int u = 0; u < EH; ++u) {
-                const int e = li + 64 * (u + EH * h);
-                v[u] = e < nn ? ab[e] : 0.f;
-            }
+                for (int u = 0; u < NB / 2; ++u) {
+                    const int k = u + (NB / 2) * h;
+                    v[u] = (k < n && li < n && k <= li) ? ab[k * n + li] : 0.f;
+                }
 #pragma unroll
-            for (int u = 0; u < EH; ++u) {
-                const int e = li + 64 * (u + EH * h);
-                const int k = (int)(((float)e + 0.5f) * rn), j = e - k * n;
-                if (e < nn && k <= j) M[k * LD + j] = v[u];
+                for (int u = 0; u < NB / 2; ++u) {
+                    const int k = u + (NB / 2) * h;
+                    if (k <= li && li < NB) M[k * LD + li] = li < n ? v[u] : (k == li ? 1.f : 0.f);
+                }
             }
         }
         wave_sync();
@@ -506,17 +503,24 @@ k_varlen_wave(const float* __restrict__ a, float* x, const int64_t* __restrict__
             }
         }
         wave_sync();
-        // rows of X, all read from LDS before the stores
-        // coalesced: element e = lane + 64 u of the dense n x n result
-        // coalesced: element e = lane + 64 u of the dense n x n result
-        li = lane;
+        // rows of X (row i in lanes j < n, the mirror below the diagonal when
+        // filling), read from LDS in batches of sixteen rows before their stores
+        int li = lane;
         asm volatile("" : "+v"(li));
 #pragma unroll
-        for (int u = 0; u < 2 * EH; ++u) {
-            const int e = li + 64 * u, ee = e < nn ? e : 0;
-            const int i = (int)(((float)ee + 0.5f) * rn), j = ee - i * n;
-            const float w = j >= i ? M[i * LD + j] : M[j * LD + i];
-            if (e < nn && (j >= i || fill)) xb[e] = fail ? __builtin_nanf("") : w;
+        for (int i0 = 0; i0 < NB; i0 += 16) {
+            float w[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int i = i0 + u;
+                w[u] = li >= i ? M[i * LD + li] : M[li * LD + i];
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int i = i0 + u;
+                if (i < n && li < n && (li >= i || fill))
+                    xb[i * n + li] = fail ? __builtin_nanf("") : w[u];
+            }
         }
         if (lane == 0 && info) info[b] = fail;
         t = t2;
