@@ -331,27 +331,20 @@ k_varlen_wave(const float* __restrict__ a, float* x, const int64_t* __restrict__
         const int t2 = grab();
         const int b2 = t2 < nbig ? item(t2) : 0;
         // rows of A (row k in lanes j < n, one uniform base address per row),
-        // half of them in flight at once; their upper triangle goes to LDS,
-        // the identity beyond n.  The lane index goes through an opaque copy
-        // so that the per-row masks and addresses are not hoisted out of the
-        // loop (they would hold registers for the whole kernel).
+        // all in flight at once; their upper triangle goes to LDS, the
+        // identity beyond n.  The lane index goes through an opaque copy so
+        // that the per-row masks and addresses are not hoisted out of the loop
+        // (they would hold registers for the whole kernel).
         wave_sync();                                     // the last matrix is stored
         {
             int li = lane;
             asm volatile("" : "+v"(li));
-            for (int h = 0; h < 2; ++h) {
-                float v[NB / 2];
+            float v[NB];
 #pragma unroll
-                for (int u = 0; u < NB / 2; ++u) {
-                    const int k = u + (NB / 2) * h;
-                    v[u] = (k < n && li < n && k <= li) ? ab[k * n + li] : 0.f;
-                }
+            for (int k = 0; k < NB; ++k) v[k] = (k < n && li < n && k <= li) ? ab[k * n + li] : 0.f;
 #pragma unroll
-                for (int u = 0; u < NB / 2; ++u) {
-                    const int k = u + (NB / 2) * h;
-                    if (k <= li && li < NB) M[k * LD + li] = li < n ? v[u] : (k == li ? 1.f : 0.f);
-                }
-            }
+            for (int k = 0; k < NB; ++k)
+                if (k <= li && li < NB) M[k * LD + li] = li < n ? v[k] : (k == li ? 1.f : 0.f);
         }
         wave_sync();
         if (MIXED && lane < NB) dl[lane] = lane < n ? (double)M[lane * LD + lane] : 1.0;
