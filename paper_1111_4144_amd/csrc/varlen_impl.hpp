@@ -251,8 +251,7 @@ k_varlen_big(const V* __restrict__ a, V* x, const int64_t* __restrict__ offs,
 // The last bucket for real float matrices by Cholesky without refinement:
 // one wave per matrix, padded with the identity to order NB (64, 48 or 32,
 // one launch each), no workgroup barriers, nine to eighteen matrices in
-// flight per compute unit.  R and Y = R^{-1} by
-// 16-column sub-blocks: the diagonal sub-block in registers (one lane per
+// flight per compute unit.  R and Y = R^{-1} by 16-column sub-blocks: the diagonal sub-block in registers (one lane per
 // column, rows reach the other lanes by readlane), its panel row and the
 // trailing update as MFMA 16 x 16 x 4 tiles; then the off-diagonal blocks of
 // Y bottom-up, Y_{a,>a} = -Y_aa (R_{a,>a} Y_{>a,>a}), and X = Y Y^T (the
@@ -265,8 +264,9 @@ k_varlen_big(const V* __restrict__ a, V* x, const int64_t* __restrict__ offs,
 // where R was: the off-diagonal tiles as they finish, the diagonal tiles
 // (which overwrite the diagonal of Y) last.  Row pitch 68 keeps the MFMA
 // operand reads of rows and of columns free of bank conflicts.  A is read
-// and X written as the dense n x n arrays they are (coalesced), and the next
-// matrix's index and offset are fetched while the current one runs.
+// and X written row by row (one uniform base address per row, all rows of A
+// in flight at once), and the next matrix's index and offset are fetched
+// while the current one runs.
 constexpr int VW_LD = 68;
 template <int NB, int MIXED>
 constexpr size_t vw_smem()
@@ -277,7 +277,7 @@ constexpr size_t vw_smem()
 // NB = 64 takes the orders 49..64 (tiles [0, tile_end[49]), counter
 // next_big), NB = 48 the orders 33..48 and NB = 32 those below 33 when the
 // bucket starts there: less work per matrix and smaller LDS arrays, so
-// twelve and sixteen waves per compute unit instead of nine.
+// twelve and eighteen waves per compute unit instead of nine.
 template <int NB, int MIXED>
 __global__ void __launch_bounds__(64, 3)
 k_varlen_wave(const float* __restrict__ a, float* x, const int64_t* __restrict__ offs,
