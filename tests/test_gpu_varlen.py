@@ -99,10 +99,12 @@ def test_varlen_edge_cases():
 def test_varlen_last_bucket_edge_cases(prec, method, fill):
     """The last bucket of a real float batch without refinement: every order
     33..64, a failing pivot near the end of an order-63 matrix, a failing first
-    pivot, and with fill_lower off the lower triangles left untouched."""
+    pivot, failing pivots in the orders padded to 48 (the first of the second
+    sub-block, the last one), and with fill_lower off the lower triangles left
+    untouched."""
     t = torch_cuda()
     from paper_1111_4144_amd import api
-    sizes = np.concatenate([np.arange(33, 65), [63, 57, 2, 40]]).astype(np.int32)
+    sizes = np.concatenate([np.arange(33, 65), [63, 57, 2, 40, 48, 33]]).astype(np.int32)
     offs = np.zeros(len(sizes), np.int64)
     offs[1:] = np.cumsum(sizes.astype(np.int64) ** 2)[:-1]
     rng = np.random.default_rng(31)
@@ -110,7 +112,8 @@ def test_varlen_last_bucket_edge_cases(prec, method, fill):
     for b, n in enumerate(sizes):
         a = G.random_hpd(rng, 1, int(n), shift=0.5, complex_=False)[0]
         packed[offs[b]:offs[b] + n * n] = a.astype(np.float32).ravel()
-    bad = {len(sizes) - 4: 62, len(sizes) - 3: 1}     # order 63: pivot 62; order 57: pivot 1
+    # order 63: pivot 62; order 57: pivot 1; order 48: pivot 17; order 33: pivot 33
+    bad = {len(sizes) - 6: 62, len(sizes) - 5: 1, len(sizes) - 2: 17, len(sizes) - 1: 33}
     for b, piv in bad.items():
         n = int(sizes[b])
         m = np.eye(n, dtype=np.float32)
