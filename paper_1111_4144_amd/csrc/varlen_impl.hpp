@@ -385,6 +385,15 @@ k_varlen_wave(const float* __restrict__ a, float* x, const int64_t* __restrict__
 #pragma unroll
                     for (int k = i + 1; k < SB; ++k) c[k] -= lf_bcast(c[i], k) * c[i];
                 }
+                // R_bb above the diagonal to LDS first: the back-substitution
+                // reads its entries from there (one LDS broadcast read each
+                // instead of a cross-lane move on the vector unit)
+                if (j < SB) {
+#pragma unroll
+                    for (int k = 0; k < SB; ++k)
+                        if (k < j) M[(b0 + k) * LD + b0 + j] = c[k];
+                }
+                wave_sync();
                 // column j of Y_bb bottom-up, y_kj = -s_k sum_{m > k} r_km y_mj,
                 // each y_mj added to every row above it as soon as it is known
                 // (two dependent operations per row instead of a serial sum)
@@ -395,14 +404,12 @@ k_varlen_wave(const float* __restrict__ a, float* x, const int64_t* __restrict__
                 for (int m = SB - 1; m >= 0; --m) {
                     y[m] = (j > m) ? -sv[m] * acc[m] : ((j == m) ? sv[m] : 0.f);
 #pragma unroll
-                    for (int k = 0; k < m; ++k) acc[k] += lf_bcast(c[k], m) * y[m];
+                    for (int k = 0; k < m; ++k) acc[k] += M[(b0 + k) * LD + b0 + m] * y[m];
                 }
                 if (j < SB) {
 #pragma unroll
-                    for (int k = 0; k < SB; ++k) {
-                        if (k < j) M[(b0 + k) * LD + b0 + j] = c[k];
+                    for (int k = 0; k < SB; ++k)
                         if (k <= j) M[(b0 + j) * LD + b0 + k] = y[k];
-                    }
                 }
             }
             wave_sync();
