@@ -291,8 +291,11 @@ k_varlen_wave(const float* __restrict__ a, float* x, const int64_t* __restrict__
     float* M = reinterpret_cast<float*>(smem_raw);
     double* dl = reinterpret_cast<double*>(M + NB * LD);
     const int lane = threadIdx.x, g = lane / 16, cc = lane % 16;
-    // y_ij of Y = R^{-1}, zero below its diagonal
+    // y_ij of Y = R^{-1}, zero below its diagonal; Yz once the upper parts of
+    // the diagonal blocks hold zeros (every read below Y's diagonal falls
+    // there: the operands below never cross blocks that way)
     auto Y = [&](int i, int j) { return i <= j ? M[j * LD + i] : 0.f; };
+    auto Yz = [&](int i, int j) { return M[j * LD + i]; };
     auto row = [&](int v) { return mfma_acc<float>::row(g, v); };
     // one wave per workgroup: LDS writes by one lane reach the reads other
     // lanes issue later in program order, so ordering needs no barrier, only
@@ -452,6 +455,15 @@ k_varlen_wave(const float* __restrict__ a, float* x, const int64_t* __restrict__
             }
             wave_sync();
         }
+        // R's diagonal blocks are not read again: zero their upper parts
+        if (lane < NB) {
+#pragma unroll
+            for (int u = 0; u < 15; ++u) {
+                const int k = (lane & ~15) + u;
+                if (k < lane) M[k * LD + lane] = 0.f;
+            }
+        }
+        wave_sync();
         // ---- off-diagonal blocks of Y, block rows bottom-up, one column tile
         // at a time: T = R_{a,>a} Y_{>a,>a}, then Y_{a,>a} = -Y_aa T
         for (int aa = NSB - 2; aa >= 0; --aa) {
@@ -461,12 +473,12 @@ k_varlen_wave(const float* __restrict__ a, float* x, const int64_t* __restrict__
                 Acc d = Acc{0, 0, 0, 0};
                 lf_tile<float>(d, 16 * (tc + 1), g, cc,
                                [&](int r, int k) { return M[(a0 + r) * LD + b1 + k]; },
-                               [&](int k, int cl) { return Y(b1 + k, c0 + cl); });
+                               [&](int k, int cl) { return Yz(b1 + k, c0 + cl); });
 #pragma unroll
                 for (int v = 0; v < 4; ++v) M[(c0 + cc) * LD + a0 + row(v)] = d[v];
                 wave_sync();
                 Acc e = Acc{0, 0, 0, 0};
-                lf_tile<float>(e, SB, g, cc, [&](int r, int k) { return Y(a0 + r, a0 + k); },
+                lf_tile<float>(e, SB, g, cc, [&](int r, int k) { return Yz(a0 + r, a0 + k); },
                                [&](int k, int cl) { return M[(c0 + cl) * LD + a0 + k]; });
 #pragma unroll
                 for (int v = 0; v < 4; ++v) M[(c0 + cc) * LD + a0 + row(v)] = -e[v];
@@ -483,8 +495,8 @@ k_varlen_wave(const float* __restrict__ a, float* x, const int64_t* __restrict__
             for (int tr = 0; tr <= tc; ++tr) {
                 Acc d = Acc{0, 0, 0, 0};
                 lf_tile<float>(d, NB - 16 * tc, g, cc,
-                               [&](int r, int k) { return Y(16 * tr + r, 16 * tc + k); },
-                               [&](int k, int cl) { return Y(16 * tc + cl, 16 * tc + k); });
+                               [&](int r, int k) { return Yz(16 * tr + r, 16 * tc + k); },
+                               [&](int k, int cl) { return Yz(16 * tc + cl, 16 * tc + k); });
                 if (tr < tc) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) M[(16 * tr + row(v)) * LD + 16 * tc + cc] = d[v];
