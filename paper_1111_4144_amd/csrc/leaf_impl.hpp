@@ -1,7 +1,8 @@
 // leaf_impl.hpp -- Cholesky of one NB x NB block and its inverse factor
 // Y = R^{-1} with the updates on the matrix cores, one workgroup of four
-// waves, the block in LDS.  Shared by the large-order factorisation (its
-// diagonal blocks) and the uneven batch (whole matrices of orders up to 64).
+// waves, the block in LDS: the diagonal blocks of the large-order
+// factorisation.  Its MFMA tile and broadcast helpers also serve the uneven
+// batch's one-wave kernel.
 //
 // Sub-blocks of LF_SB columns: wave 0 factors the diagonal sub-block in
 // registers (one lane per column; row i of R reaches every lane by readlane

@@ -1,4 +1,4 @@
-// varlen_impl.hpp -- one persistent launch for a packed batch of matrices of
+// varlen_impl.hpp -- persistent launches for a packed batch of matrices of
 // uneven orders (1..64).  Included by one translation unit per element type.
 //
 // Device-side prologue (no host synchronisation, capturable in a HIP graph):
@@ -6,20 +6,20 @@
 //   2. scan    orders are laid out largest first: per order n its first item
 //              in the sorted index list and its tile range;
 //   3. scatter every matrix index into the sorted list.
-// Tiles: an order n <= 8 tile is up to 64 matrices (one lane each, registers);
-// 9..16 up to 16 or 4 matrices (4- or 16-lane groups padded to 16 with the
-// identity, which leaves the n x n block exact); 17..32 up to 2 (LDS-resident, one lane
-// per column) and 33..64 one matrix: one wave on the matrix cores for real
-// float by Cholesky without refinement, else four waves with four lanes per
-// column (LDS-resident).  The edge of the last bucket (33) can move down to 25
-// or 17 (a tuned choice): those orders then go to the last bucket's kernel.
-// Persistent kernels take tiles from their own atomic counters until none
-// are left (every wave reaches that exit): first the last bucket (one kernel,
-// or on the matrix cores one per padded order 64, 48 and 32), then the rest,
-// largest orders first within each.  The
-// order of a tile comes from the plan's per-order table held one order per
-// lane (a ballot, no dependent loads).  Results do not depend on which wave
-// takes which tile.
+// Tiles: an order n <= 8 tile is up to 64 matrices (one lane each,
+// registers); 9..16 up to 16 or 4 matrices (4- or 16-lane groups padded to
+// 16 with the identity, which leaves the n x n block exact); 17..32 up to 2
+// (LDS-resident, one lane per column) and 33..64 one matrix: one wave on the
+// matrix cores for real float by Cholesky without refinement, else four
+// waves with four lanes per column (LDS-resident).  The edge of the last
+// bucket (33) can move down to 25 or 17 (a tuned choice): those orders then
+// go to the last bucket's kernel.  Persistent kernels take tiles from their
+// own atomic counters until none are left (every wave reaches that exit):
+// first the last bucket (one kernel, or on the matrix cores one per padded
+// order 64, 48 and 32), then the rest, largest orders first within each.
+// The order of a tile comes from the plan's per-order table held one order
+// per lane (a ballot, no dependent loads).  Results do not depend on which
+// wave takes which tile.
 #pragma once
 
 #include "group_impl.hpp"
@@ -36,7 +36,7 @@ struct VarlenPlan {
     int next_48;           // the same for its orders 33..48 (starts at tile_end[49])
     int next_32;           // the same for its orders up to 32 (starts at tile_end[33])
     int nbig;              // tiles of orders big_from..64 (one matrix each, first in the order)
-    int big_from;          // smallest order of the four-waves-per-matrix kernel (17, 25 or 33)
+    int big_from;          // smallest order of the last bucket (17, 25 or 33)
     int count[65];         // matrices per order
     int item_start[65];    // first position of order n in the sorted list
     int tile_start[65];    // tile range of order n: [tile_start, tile_end)
