@@ -1,8 +1,14 @@
-"""The MIMO batch at its full size (524,288 complex64 matrices per order),
-launched as the benchmark launches it (engines chosen by the autotuner on
-this device, mixed precision with one Newton-Schulz step, and plain FP64 on
-the same matrices in complex128), checked against the oracle on sampled
-matrices (the first, the last and 2046 drawn at random)."""
+"""The batched workloads at their full sizes, launched as the benchmark
+launches them, checked against the oracle on sampled matrices:
+
+* the MIMO batch (524,288 complex64 matrices per order; engines chosen by the
+  autotuner on this device, mixed precision with one Newton-Schulz step, and
+  plain FP64 on the same matrices in complex128): the first, the last and
+  2046 drawn at random;
+* the uneven batch (262,144 real float matrices of orders 2..64, packed; the
+  bucket edge chosen by the tuner on the batch, and the lowest edge, which
+  sends orders 17..64 to the matrix cores): the first, the last and three of
+  every order."""
 from __future__ import annotations
 
 import numpy as np
@@ -40,5 +46,45 @@ def test_mimo_full_size_sampled(n):
         y = api.inverse(A.to(torch.complex128)).cpu().numpy()[idx]
         e, r = assert_within(y, ref, a[idx], TOL_FP64, "full-size %dx%d plain c128" % (n, n))
         print("%dx%d plain FP64: max rel err %.3e, max err/kappa %.3e" % (n, n, e, r))
+    finally:
+        api.autotune_clear()
+
+
+VARLEN_COUNT = 262144
+
+
+def test_varlen_full_size_sampled():
+    torch = torch_cuda()
+    from paper_1111_4144_amd import api
+    packed, sizes, offs = I.varlen_spd(VARLEN_COUNT)
+    P = torch.from_numpy(packed).cuda()
+    S = torch.from_numpy(sizes).cuda()
+    OF = torch.from_numpy(offs).cuda()
+    ws = torch.empty(api.varlen_workspace_bytes(P, VARLEN_COUNT), dtype=torch.uint8, device="cuda")
+    rng = np.random.default_rng(47)
+    pick = [0, VARLEN_COUNT - 1]
+    for n in np.unique(sizes):
+        pick += list(rng.choice(np.nonzero(sizes == n)[0], 3, replace=False))
+    pick = np.unique(np.array(pick))
+    api.autotune_clear()
+    try:
+        tuned = api.autotune_varlen(P, S, OF, n_max=64, workspace=ws)
+        for edge in sorted({tuned, 17}):
+            api.tune_set(torch.float32, 0, edge)
+            X, info = api.inverse_varlen(P, S, OF, n_max=64, workspace=ws, return_info=True)
+            assert not info.cpu().numpy().any()
+            x = X.cpu().numpy()
+            worst = 0.0
+            for n in np.unique(sizes[pick]):
+                bs = pick[sizes[pick] == n]
+                a = np.stack([packed[offs[b]:offs[b] + n * n].reshape(n, n) for b in bs])
+                xs = np.stack([x[offs[b]:offs[b] + n * n].reshape(n, n) for b in bs])
+                ref, io = O.inv_prop(a.astype(np.float64))
+                assert not io.any()
+                e, r = assert_within(xs.astype(np.float64), ref, a.astype(np.float64), TOL_FP32,
+                                     "full-size uneven batch, edge %d, order %d" % (edge, n))
+                worst = max(worst, r)
+            print("uneven batch, edge %d: %d sampled matrices, max err/kappa %.3e"
+                  % (edge, len(pick), worst))
     finally:
         api.autotune_clear()
