@@ -8,7 +8,11 @@ launches them, checked against the oracle on sampled matrices:
 * the uneven batch (262,144 real float matrices of orders 2..64, packed; the
   bucket edge chosen by the tuner on the batch, and the lowest edge, which
   sends orders 17..64 to the matrix cores): the first, the last and three of
-  every order."""
+  every order;
+* the differentiation workload (65,536 complex64 16x16, forward in mixed
+  precision with one Newton-Schulz step, then the hand-written backward):
+  the gradient of the first, the last and 2046 drawn at random against the
+  oracle's analytic gradient at the exact inverse."""
 from __future__ import annotations
 
 import numpy as np
@@ -16,7 +20,7 @@ import pytest
 
 import oracle as O
 from paper_1111_4144_amd import inputs as I
-from tests.helpers import TOL_FP32, TOL_FP64, assert_within, torch_cuda
+from tests.helpers import TOL_FP32, TOL_FP64, assert_within, kappas, rel_err, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -88,3 +92,28 @@ def test_varlen_full_size_sampled():
                   % (edge, len(pick), worst))
     finally:
         api.autotune_clear()
+
+
+GRAD_COUNT = 65536
+
+
+def test_differentiation_full_size_sampled():
+    torch = torch_cuda()
+    from paper_1111_4144_amd import api
+    a, g = I.grad_16(count=GRAD_COUNT)
+    A = torch.from_numpy(a).cuda().requires_grad_(True)
+    X = api.CholInverse.apply(A, "chol", "mixed", 1)
+    X.backward(torch.from_numpy(g).cuda())
+    rng = np.random.default_rng(53)
+    idx = np.unique(np.concatenate([[0, GRAD_COUNT - 1],
+                                    rng.choice(GRAD_COUNT, 2046, replace=False)]))
+    ga = A.grad.cpu().numpy()[idx]
+    xo, io = O.inv_prop(a[idx])
+    assert not io.any()
+    want = O.grad(xo, g[idx])
+    err = rel_err(ga, want)
+    bound = 2 * TOL_FP32 * kappas(a[idx]) + 1e-5
+    assert np.all(err <= bound), (err / bound).max()
+    assert np.array_equal(ga, np.conj(np.swapaxes(ga, -1, -2)))      # exactly Hermitian
+    print("differentiation, %d sampled of %d: max grad rel err %.3e" % (len(idx), GRAD_COUNT,
+                                                                       err.max()))
